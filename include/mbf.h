@@ -1,0 +1,234 @@
+/*
+ * mbf.h -- C ABI of libmbf: the multidimensional butterfly factorization
+ * (Li, Yang, Ying, "Multidimensional Butterfly Factorization") applied on an
+ * AMD MI355X (gfx950).
+ *
+ * The library evaluates u = K g (Section 1.1, eq. (kernel)):
+ *     u(x) = sum_{xi in Omega} K(x, xi) g(xi),  x in X,
+ * through the factorization of eq. (gbf):
+ *     K ~ U^L G^{L-1} ... G^h M^h (H^h)^* ... (H^{L-1})^* (V^L)^*,
+ * applied right to left on the GPU (Section 2.5: cost = number of nonzeros).
+ * Singular kernels e^{2 pi i Phi(x, xi)} use the polar split (Section 3.2)
+ * or the multiscale split K = K_C R_C + sum_t K_t R_t (Section 4.2,
+ * eq. (msumd), eq. (f1)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Ordering:  row i of K (and of u) follows the caller's order of X; column j
+ *            (and row j of g) follows the caller's order of Omega.  Tree
+ *            permutations are internal.
+ * Layout:    complex values are interleaved (re, im): complex64 = 2 floats,
+ *            complex128 = 2 doubles.  RHS blocks are column-major with a
+ *            leading dimension ld >= number of points.
+ * Ownership: g, u, v, h and workspace are device pointers owned by the caller.
+ *            A factor handle owns its device memory until mbf_destroy.
+ * Streams:   `stream` is a hipStream_t passed as void* (NULL = default
+ *            stream).  Apply calls only enqueue work: they never synchronize
+ *            and never allocate.  A factor is immutable after build/import;
+ *            concurrent applies on different streams with separate
+ *            workspaces are safe.
+ * Errors:    every call returns an mbf_status; no exception crosses the ABI.
+ *            mbf_last_error() returns a thread-local message for the last
+ *            failure on the calling thread.
+ */
+#ifndef MBF_H
+#define MBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MBF_OK = 0,
+  MBF_ERR_INVALID_ARG = -1,
+  MBF_ERR_OOM = -2,
+  MBF_ERR_CALLBACK = -3,
+  MBF_ERR_HIP = -4,
+  MBF_ERR_UNSUPPORTED = -5,
+  MBF_ERR_BUSY = -6,
+  MBF_ERR_IO = -7
+} mbf_status;
+
+/* Arithmetic of the apply.  A factor keeps one device copy per precision
+ * requested in its precision mask (bit 1 << mbf_prec).
+ *   MBF_C128      complex128 factors and vectors, FP64 arithmetic.
+ *   MBF_C64       complex64 factors and vectors, FP32 arithmetic.
+ *   MBF_C64_SPLIT_BF16  complex64 vectors; each stage block product runs on
+ *                 BF16 matrix cores as hi*hi + hi*lo + lo*hi with FP32
+ *                 accumulation (factor entry = hi + lo, both BF16).      */
+typedef enum {
+  MBF_C128 = 0,
+  MBF_C64 = 1,
+  MBF_C64_SPLIT_BF16 = 2
+} mbf_prec;
+
+typedef enum { MBF_SPLIT_NONE = 0, MBF_SPLIT_POLAR = 1, MBF_SPLIT_MULTISCALE = 2 } mbf_split;
+
+typedef struct mbf_factor_s* mbf_factor;
+
+/* Kernel-entry callback (build case (ii), Section 2.3: every entry of K can
+ * be evaluated in O(1)).  Must write out[a + b*m] = K(x[rows[a]], xi[cols[b]])
+ * as interleaved complex128 for a < m, b < k, where rows / cols index the
+ * point arrays given to mbf_build.  Return 0 on success; any other value
+ * aborts the build with MBF_ERR_CALLBACK.  Called concurrently from several
+ * host threads. */
+typedef int (*mbf_entry_cb)(void* user, int64_t m, const int64_t* rows, int64_t k,
+                            const int64_t* cols, double* out);
+
+/* Ready-made callbacks.  `user` points to an mbf_kernel_params.
+ *   mbf_kernel_dft:  K = exp(-2 pi i x.xi / n), x and xi integer coordinates
+ *                    (the 2D DFT; x.xi is reduced modulo n exactly).
+ *   mbf_kernel_fio:  Example 1 of Section 3.3, eq. (example1phi):
+ *                    K = exp(2 pi i Phi), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),
+ *                    c1 = c_scale (2 + sin 2pi x1 sin 2pi x2)/16,
+ *                    c2 = c_scale (2 + cos 2pi x1 cos 2pi x2)/16,
+ *                    x = (n1/n, n2/n), xi integer.                       */
+typedef struct {
+  int64_t n;        /* grid side */
+  double c_scale;   /* FIO only: 1 = Example 1, 0 = linear phase x.xi */
+  const double* x;  /* X points (2 doubles each), as given to mbf_build */
+  const double* xi; /* Omega points */
+} mbf_kernel_params;
+int mbf_kernel_dft(void* user, int64_t m, const int64_t* rows, int64_t k, const int64_t* cols,
+                   double* out);
+int mbf_kernel_fio(void* user, int64_t m, const int64_t* rows, int64_t k, const int64_t* cols,
+                   double* out);
+
+/* Build options.
+ *   tol        block-relative truncation: keep sigma_k > tol * sigma_1
+ *              (the paper fixes a rank r instead; max_rank caps it).
+ *   max_rank   rank cap per block (>= 1).
+ *   depth      tree depth L (both trees).  0 = automatic: uniform leaves of
+ *              leaf_side x leaf_side points on a grid of side n.
+ *   leaf_side  leaf side for depth = 0 (power of two dividing n).
+ *   grid_n     side n of the grids (needed by the polar and multiscale maps).
+ *   split      MBF_SPLIT_*.
+ *   center_side multiscale only: side of the dense center square Omega_C
+ *              (Section 4.3 uses 16).
+ *   oversample random-sampling oversampling (extra rows / columns).
+ *   seed       seed of the random sampling.
+ *   prec_mask  bit (1 << mbf_prec) for every precision to keep on device.
+ *   threads    host threads for the build (0 = hardware concurrency).      */
+typedef struct {
+  double tol;
+  int32_t max_rank;
+  int32_t depth;
+  int32_t leaf_side;
+  int32_t grid_n;
+  int32_t split;
+  int32_t center_side;
+  int32_t oversample;
+  uint64_t seed;
+  uint32_t prec_mask;
+  int32_t threads;
+} mbf_opts;
+
+/* Build a factorization from point sets and an entry callback (Section 2,
+ * case (ii)): middle-level factorization by SVD via random sampling
+ * (Sections 2.1, 2.3, eq. (Kij), form eq. (lowrank1)), then the recursive
+ * factorizations of U^h and V^h by truncated SVD (Section 2.4, eq. (blockF),
+ * form eq. (lowrank2)); polar (Section 3.2) or multiscale (Section 4.2)
+ * splits per opts->split.  x: nx points, xi: nxi points, 2 doubles each
+ * (host memory, read during the call only).  The build runs in FP64 on the
+ * host; the packed factors are copied to the current HIP device on `stream`
+ * before the call returns.  Errors: MBF_ERR_INVALID_ARG (bad sizes or
+ * options), MBF_ERR_CALLBACK (callback returned nonzero; nothing leaks),
+ * MBF_ERR_OOM, MBF_ERR_HIP. */
+mbf_status mbf_build(int32_t dim, int64_t nx, const double* x, int64_t nxi, const double* xi,
+                     mbf_entry_cb cb, void* user, const mbf_opts* opts, void* stream,
+                     mbf_factor* out);
+
+/* Import an already built factorization: the factors of eq. (gbf) as host
+ * arrays (FP64), read during the call only.  Used to apply factorizations
+ * built elsewhere.  Trees: quadtrees of depth L whose nodes are numbered in
+ * Z-order (Section 2.2, Fig. 1; child t of node i is 4i+t).  A tree is given
+ * by the Morton code of the leaf holding each point; nodes without points
+ * are absent, and the points of a leaf are ordered by increasing index.
+ * Stage s (0..L) pairs: (A at level s of T_X, B at level L-s of T_Omega),
+ * enumerated A-major, B-minor, over nonempty nodes in increasing Morton
+ * code.  h = floor(L/2).  All matrices are column-major complex128.
+ *   ranks     for s = 0..L, one int32 per stage-s pair (concatenated).
+ *   v_leaf    (V^L)^* blocks: for every nonempty Omega leaf B, V_B of size
+ *             |B| x rank_0(root, B) (y_B = V_B^* g_B).
+ *   h_blocks  for s = 0..h-1, for every A at X-level s, for every B' at
+ *             Omega-level L-s-1, for every nonempty child B of B' in order:
+ *             H_{B,A} of size rank_s(A,B) x sum_t rank_{s+1}(child_t A, B')
+ *             (columns grouped by the children of A in order); the stage
+ *             product is y_{(child_t A, B')} = sum_B H_{B,A}[:, t-group]^* y_{(A,B)}
+ *             (Section 2.4.2, mirror of eq. (blockF)).
+ *   s_mid     for every stage-h pair in pair order, rank_h values of
+ *             S = Sigma^{-1} (eq. (lowrank1), eq. (Kij)); M^h applies them.
+ *   g_blocks  for s = h..L-1, for every A at X-level s, for every B' at
+ *             Omega-level L-s-1, for every child A_t of A in order:
+ *             G_{A_t,B'} of size rank_{s+1}(A_t,B') x sum_sigma rank_s(A, child_sigma B')
+ *             (eq. (blockF), eq. (RSh2)).
+ *   u_leaf    for every X leaf A: U_A of size |A| x rank_L(A, root).
+ * Errors: MBF_ERR_INVALID_ARG when sizes are inconsistent. */
+typedef struct {
+  int32_t depth;                 /* L */
+  int64_t nx, nxi;               /* points of X and of Omega */
+  const int64_t* x_leaf_code;    /* nx Morton codes at level L */
+  const int64_t* xi_leaf_code;   /* nxi Morton codes at level L */
+  const int32_t* ranks;
+  const double* v_leaf;
+  const double* h_blocks;
+  const double* s_mid;
+  const double* g_blocks;
+  const double* u_leaf;
+} mbf_import_desc;
+
+mbf_status mbf_import(const mbf_import_desc* d, uint32_t prec_mask, void* stream, mbf_factor* out);
+
+/* Multiscale assembly (Section 4.2, eq. (f1)): K ~ K_C R_C + sum_t K_t R_t.
+ * parts[t] is a factorization of K restricted to X x Omega_t, and
+ * part_idx[t] (part_n[t] entries) lists, in that factorization's column
+ * order, the Omega indices of Omega_t.  center holds K_C as a dense
+ * column-major complex128 nx x n_center matrix on the host, center_idx its
+ * Omega indices.  The new handle takes ownership of the parts (do not
+ * destroy them separately, also on failure). */
+mbf_status mbf_multiscale_assemble(int32_t nparts, mbf_factor* parts, const int64_t* const* part_idx,
+                                   const int64_t* part_n, int64_t nxi, int64_t n_center,
+                                   const int64_t* center_idx, const double* center,
+                                   uint32_t prec_mask, void* stream, mbf_factor* out);
+
+/* Bytes of device workspace needed by an apply of nrhs columns. */
+mbf_status mbf_workspace_size(mbf_factor f, mbf_prec p, int64_t nrhs, size_t* bytes);
+
+/* u = K g.  g: nxi x nrhs (ld ldg), u: nx x nrhs (ld ldu), device memory of
+ * the precision's vector type (complex128 for MBF_C128, complex64
+ * otherwise).  Overwrites u.  Errors: MBF_ERR_INVALID_ARG (null pointer,
+ * ld too small, workspace too small), MBF_ERR_UNSUPPORTED (precision not in
+ * the factor's mask), MBF_ERR_HIP (launch failure). */
+mbf_status mbf_apply(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg, void* u,
+                     int64_t ldu, void* workspace, size_t ws_bytes, void* stream);
+
+/* v = K^* h: the chain of eq. (gbf) in reverse order with every factor
+ * conjugate-transposed.  h: nx x nrhs (ld ldh), v: nxi x nrhs (ld ldv). */
+mbf_status mbf_apply_adjoint(mbf_factor f, mbf_prec p, int64_t nrhs, const void* h, int64_t ldh,
+                             void* v, int64_t ldv, void* workspace, size_t ws_bytes, void* stream);
+
+/* Sizes of a factorization (Section 2.5, Table 1: apply cost = nnz). */
+typedef struct {
+  int32_t depth;          /* L (0 for multiscale handles) */
+  int32_t mid;            /* h */
+  int32_t nparts;         /* 1, or the number of coronas */
+  int32_t max_rank[33];   /* per stage s = 0..L: max pair rank (first part) */
+  int64_t nx, nxi;
+  int64_t nnz;            /* complex nonzeros of all factors (incl. dense center) */
+  int64_t nnz_stage_max;  /* largest single-stage block nonzeros */
+  int64_t state_rows_max; /* largest stage state (rows) */
+  uint32_t prec_mask;
+  size_t device_bytes;    /* factor bytes resident on the device */
+} mbf_info_t;
+mbf_status mbf_info(mbf_factor f, mbf_info_t* out);
+
+void mbf_destroy(mbf_factor f);
+const char* mbf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBF_H */

@@ -1,0 +1,522 @@
+// Apply kernels of the butterfly factorization (eq. (gbf), right to left)
+// and their launch sequence.  See device.h for the HBM layout.
+//
+//   leaf_project      y_B = F_B^* x[B]   (x gathered through the point index)
+//                     forward: F = V^L on Omega leaves; adjoint: F = U^L on X leaves
+//   stage             out = W_blk in  (forward)  /  out = W_blk^* in (adjoint),
+//                     one W_blk per (A, B'); the M^h scaling diag(1/sigma) is
+//                     applied in the epilogue of the stage that produces the
+//                     middle-level state
+//   leaf_reconstruct  x[A] (+)= F_A z_A  (scatter through the point index)
+//   dense_center      u += K_C g[Omega_C]       (multiscale, eq. (f1))
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "device.h"
+#include "stage_mfma.h"
+
+namespace mbf {
+
+template <typename T>
+struct cx;
+template <>
+struct cx<float> {
+  using t = float2;
+};
+template <>
+struct cx<double> {
+  using t = double2;
+};
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ void cfma(C& acc, C a, C b) {
+  acc.x += a.x * b.x - a.y * b.y;
+  acc.y += a.x * b.y + a.y * b.x;
+}
+template <typename C>
+__device__ __forceinline__ C cconj(C a) {
+  a.y = -a.y;
+  return a;
+}
+template <typename C>
+__device__ __forceinline__ C czero() {
+  C r;
+  r.x = 0;
+  r.y = 0;
+  return r;
+}
+
+__device__ __forceinline__ int32_t group_row(const BlockDesc& d, int32_t i) {
+  const int t = (i >= d.ms[1]) + (i >= d.ms[2]) + (i >= d.ms[3]);
+  return d.orow[t] + i - d.ms[t];
+}
+
+// ------------------------------------------------------------------ stage
+// Tile of 64 output rows x 32 right-hand sides per pass, 16-deep reduction
+// chunks staged in LDS; each of the 256 threads owns 4 x 2 outputs.
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) void k_stage(const BlockDesc* __restrict__ blk,
+                                               const typename cx<T>::t* __restrict__ W,
+                                               const typename cx<T>::t* __restrict__ in,
+                                               int64_t ld_in, typename cx<T>::t* __restrict__ out,
+                                               int64_t ld_out, int nrhs,
+                                               const T* __restrict__ scale) {
+  using C = typename cx<T>::t;
+  constexpr int BM = 64, BN = 32, BK = 16;
+  __shared__ C As[BK][BM + 1];
+  __shared__ C Bs[BN][BK + 1];
+  const BlockDesc d = blk[blockIdx.x];
+  const int R = ADJ ? d.K : d.M;
+  const int Q = ADJ ? d.M : d.K;
+  const int n0 = blockIdx.y * BN;
+  const C* Wb = W + d.w_off;
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+  for (int r0 = 0; r0 < R; r0 += BM) {
+    C acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = czero<C>();
+    for (int q0 = 0; q0 < Q; q0 += BK) {
+      for (int e = tid; e < BK * BM; e += 256) {
+        int q, r;
+        if (!ADJ) {
+          r = e % BM;
+          q = e / BM;
+        } else {
+          q = e % BK;
+          r = e / BK;
+        }
+        const int gr = r0 + r, gq = q0 + q;
+        C v = czero<C>();
+        if (gr < R && gq < Q)
+          v = ADJ ? cconj(Wb[(int64_t)gr * d.M + gq]) : Wb[(int64_t)gq * d.M + gr];
+        As[q][r] = v;
+      }
+      for (int e = tid; e < BK * BN; e += 256) {
+        const int q = e % BK, n = e / BK;
+        const int gq = q0 + q, gn = n0 + n;
+        C v = czero<C>();
+        if (gq < Q && gn < nrhs) {
+          const int32_t row = ADJ ? group_row(d, gq) : d.in_row + gq;
+          v = in[(int64_t)gn * ld_in + row];
+        }
+        Bs[n][q] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < BK; ++q) {
+        C a[4], b[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = As[q][tr + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[tc + 16 * j][q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) cfma(acc[i][j], a[i], b[j]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gr = r0 + tr + 16 * i, gn = n0 + tc + 16 * j;
+        if (gr < R && gn < nrhs) {
+          const int32_t row = ADJ ? d.in_row + gr : group_row(d, gr);
+          C v = acc[i][j];
+          if (scale) {
+            const T s = scale[row];
+            v.x *= s;
+            v.y *= s;
+          }
+          out[(int64_t)gn * ld_out + row] = v;
+        }
+      }
+  }
+}
+
+// ------------------------------------------------------------------ leaves
+// out[row + k, n] = sum_i conj(F[i + k np]) x[idx[p_off + i], n]
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_project(const LeafDesc* __restrict__ leaves,
+                                                      const typename cx<T>::t* __restrict__ F,
+                                                      const int32_t* __restrict__ idx,
+                                                      const typename cx<T>::t* __restrict__ x,
+                                                      int64_t ldx, typename cx<T>::t* __restrict__ out,
+                                                      int64_t ld_out, int nrhs,
+                                                      const T* __restrict__ scale) {
+  using C = typename cx<T>::t;
+  __shared__ C Xs[64][33];
+  __shared__ C Fs[64][65];
+  const LeafDesc d = leaves[blockIdx.x];
+  const int n0 = blockIdx.y * 32;
+  const int tid = threadIdx.x;
+  const int tk = tid & 63, tn = tid >> 6;
+  const C* Fb = F + d.f_off;
+  for (int k0 = 0; k0 < d.r; k0 += 64) {
+    C acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
+    for (int i0 = 0; i0 < d.np; i0 += 64) {
+      for (int e = tid; e < 64 * 32; e += 256) {
+        const int i = e & 63, n = e >> 6;
+        C v = czero<C>();
+        if (i0 + i < d.np && n0 + n < nrhs) v = x[(int64_t)(n0 + n) * ldx + idx[d.p_off + i0 + i]];
+        Xs[i][n] = v;
+      }
+      for (int e = tid; e < 64 * 64; e += 256) {
+        const int i = e & 63, k = e >> 6;
+        C v = czero<C>();
+        if (i0 + i < d.np && k0 + k < d.r) v = cconj(Fb[(int64_t)(k0 + k) * d.np + i0 + i]);
+        Fs[i][k] = v;
+      }
+      __syncthreads();
+      const int ilim = min(64, d.np - i0);
+      for (int i = 0; i < ilim; ++i) {
+        const C f = Fs[i][tk];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cfma(acc[j], f, Xs[i][tn + 4 * j]);
+      }
+      __syncthreads();
+    }
+    if (k0 + tk < d.r) {
+      const int32_t row = d.row + k0 + tk;
+      const T s = scale ? scale[row] : T(1);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + tn + 4 * j;
+        if (n < nrhs) {
+          C v = acc[j];
+          v.x *= s;
+          v.y *= s;
+          out[(int64_t)n * ld_out + row] = v;
+        }
+      }
+    }
+  }
+}
+
+// x[idx[p_off + i], n] (+)= sum_k F[i + k np] z[row + k, n]
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __restrict__ leaves,
+                                                          const typename cx<T>::t* __restrict__ F,
+                                                          const int32_t* __restrict__ idx,
+                                                          const typename cx<T>::t* __restrict__ z,
+                                                          int64_t ldz, typename cx<T>::t* __restrict__ x,
+                                                          int64_t ldx, int nrhs, int accumulate) {
+  using C = typename cx<T>::t;
+  __shared__ C Zs[64][33];
+  const LeafDesc d = leaves[blockIdx.x];
+  const int n0 = blockIdx.y * 32;
+  const int tid = threadIdx.x;
+  const int ti = tid & 63, tn = tid >> 6;
+  const C* Fb = F + d.f_off;
+  for (int i0 = 0; i0 < d.np; i0 += 64) {
+    C acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
+    for (int k0 = 0; k0 < d.r; k0 += 64) {
+      for (int e = tid; e < 64 * 32; e += 256) {
+        const int k = e & 63, n = e >> 6;
+        C v = czero<C>();
+        if (k0 + k < d.r && n0 + n < nrhs) v = z[(int64_t)(n0 + n) * ldz + d.row + k0 + k];
+        Zs[k][n] = v;
+      }
+      __syncthreads();
+      if (i0 + ti < d.np) {
+        const int klim = min(64, d.r - k0);
+        for (int k = 0; k < klim; ++k) {
+          const C f = Fb[(int64_t)(k0 + k) * d.np + i0 + ti];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) cfma(acc[j], f, Zs[k][tn + 4 * j]);
+        }
+      }
+      __syncthreads();
+    }
+    if (i0 + ti < d.np) {
+      const int64_t p = idx[d.p_off + i0 + ti];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + tn + 4 * j;
+        if (n < nrhs) {
+          C v = acc[j];
+          C* o = x + (int64_t)n * ldx + p;
+          if (accumulate) {
+            C w = *o;
+            v.x += w.x;
+            v.y += w.y;
+          }
+          *o = v;
+        }
+      }
+    }
+  }
+}
+
+// u[i, n] (+)= sum_k KC[i + k nx] g[cidx[k], n]     (dense center, forward)
+template <typename T>
+__global__ __launch_bounds__(256) void k_center_fwd(const typename cx<T>::t* __restrict__ KC,
+                                                    const int32_t* __restrict__ cidx, int64_t nx,
+                                                    int32_t nc, const typename cx<T>::t* __restrict__ g,
+                                                    int64_t ldg, typename cx<T>::t* __restrict__ u,
+                                                    int64_t ldu, int nrhs, int accumulate) {
+  using C = typename cx<T>::t;
+  __shared__ C Gs[64][33];
+  const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int tn = threadIdx.x >> 6;
+  const int n0 = blockIdx.y * 32;
+  C acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
+  for (int k0 = 0; k0 < nc; k0 += 64) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int k = e & 63, n = e >> 6;
+      C v = czero<C>();
+      if (k0 + k < nc && n0 + n < nrhs) v = g[(int64_t)(n0 + n) * ldg + cidx[k0 + k]];
+      Gs[k][n] = v;
+    }
+    __syncthreads();
+    if (i < nx) {
+      const int klim = min(64, nc - k0);
+      for (int k = 0; k < klim; ++k) {
+        const C f = KC[(int64_t)(k0 + k) * nx + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cfma(acc[j], f, Gs[k][tn + 4 * j]);
+      }
+    }
+    __syncthreads();
+  }
+  if (i < nx) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = n0 + tn + 4 * j;
+      if (n < nrhs) {
+        C v = acc[j];
+        C* o = u + (int64_t)n * ldu + i;
+        if (accumulate) {
+          C w = *o;
+          v.x += w.x;
+          v.y += w.y;
+        }
+        *o = v;
+      }
+    }
+  }
+}
+
+// Adjoint of the dense center, pass 1: partial[chunk, k, n] = sum over the
+// chunk's rows i of conj(KC[i + k nx]) h[i, n].  One workgroup per
+// (chunk of 4096 rows, k tile of 64, n tile of 4).
+template <typename T>
+__global__ __launch_bounds__(256) void k_center_adj_partial(const typename cx<T>::t* __restrict__ KC,
+                                                            int64_t nx, int32_t nc,
+                                                            const typename cx<T>::t* __restrict__ h,
+                                                            int64_t ldh, int nrhs,
+                                                            typename cx<T>::t* __restrict__ part) {
+  using C = typename cx<T>::t;
+  constexpr int CH = 4096;
+  __shared__ C red[4][64][5];
+  const int k = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int w = threadIdx.x >> 6;  // 4 row slices
+  const int64_t i0 = (int64_t)blockIdx.x * CH;
+  const int n0 = blockIdx.z * 4;
+  C acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = czero<C>();
+  if (k < nc) {
+    for (int64_t i = i0 + w; i < min(i0 + CH, nx); i += 4) {
+      const C f = cconj(KC[(int64_t)k * nx + i]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (n0 + j < nrhs) cfma(acc[j], f, h[(int64_t)(n0 + j) * ldh + i]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) red[w][threadIdx.x & 63][j] = acc[j];
+  __syncthreads();
+  if (w == 0 && k < nc) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      C s = red[0][threadIdx.x & 63][j];
+      for (int q = 1; q < 4; ++q) {
+        s.x += red[q][threadIdx.x & 63][j].x;
+        s.y += red[q][threadIdx.x & 63][j].y;
+      }
+      if (n0 + j < nrhs) part[((int64_t)blockIdx.x * nrhs + n0 + j) * nc + k] = s;
+    }
+  }
+}
+
+// Pass 2: v[cidx[k], n] = sum over chunks of partial[chunk, k, n].
+template <typename T>
+__global__ __launch_bounds__(256) void k_center_adj_reduce(const typename cx<T>::t* __restrict__ part,
+                                                           int nchunk, int32_t nc,
+                                                           const int32_t* __restrict__ cidx,
+                                                           typename cx<T>::t* __restrict__ v,
+                                                           int64_t ldv, int nrhs) {
+  using C = typename cx<T>::t;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nc * nrhs) return;
+  const int k = (int)(e % nc), n = (int)(e / nc);
+  C s = czero<C>();
+  for (int c = 0; c < nchunk; ++c) {
+    const C p = part[((int64_t)c * nrhs + n) * nc + k];
+    s.x += p.x;
+    s.y += p.y;
+  }
+  v[(int64_t)n * ldv + cidx[k]] = s;
+}
+
+// ------------------------------------------------------------------ launch
+namespace {
+
+constexpr int kTN = 32;  // RHS per workgroup in the generic kernels
+
+inline Error hip_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return {MBF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+  return {MBF_OK, ""};
+}
+
+inline unsigned ntiles(int64_t nrhs) { return (unsigned)((nrhs + kTN - 1) / kTN); }
+
+template <typename T>
+Error run_part(const DevPart& P, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
+               void* out, int64_t ldout, void* ws, int64_t ws_ld, bool accumulate, hipStream_t st) {
+  using C = typename cx<T>::t;
+  const PrecData& pd = P.prec[prec];
+  C* buf[2] = {reinterpret_cast<C*>(ws), reinterpret_cast<C*>(ws) + ws_ld * nrhs};
+  const C* W = reinterpret_cast<const C*>(pd.W);
+  const T* S = reinterpret_cast<const T*>(pd.S);
+  const int L = P.L, m = P.m;
+  const unsigned nt = ntiles(nrhs);
+  const int ni = (int)nrhs;
+  if (!adj) {
+    if (P.n_vleaf > 0)
+      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf,
+                         reinterpret_cast<const C*>(pd.V0), P.d_vidx, reinterpret_cast<const C*>(in),
+                         ldin, buf[0], P.ld[0], ni, m == 0 ? S : nullptr);
+    for (int s = 0; s < L; ++s) {
+      if (P.nblk[s] == 0) continue;
+      const T* sc = (s == m - 1) ? S : nullptr;
+      const BlockDesc* bd = P.d_blk + P.blk_first[s];
+      if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
+        Error e = launch_stage_mfma(P, s, prec, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1],
+                                    P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
+        if (e.st != MBF_OK) return e;
+      } else {
+        hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W,
+                           buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni, sc);
+      }
+    }
+    if (P.n_uleaf > 0)
+      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf,
+                         reinterpret_cast<const C*>(pd.UL), P.d_uidx, buf[L & 1], P.ld[L],
+                         reinterpret_cast<C*>(out), ldout, ni, accumulate ? 1 : 0);
+  } else {
+    if (P.n_uleaf > 0)
+      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf,
+                         reinterpret_cast<const C*>(pd.UL), P.d_uidx, reinterpret_cast<const C*>(in),
+                         ldin, buf[L & 1], P.ld[L], ni, m == L ? S : nullptr);
+    for (int s = L - 1; s >= 0; --s) {
+      if (P.nblk[s] == 0) continue;
+      const T* sc = (s == m) ? S : nullptr;
+      const BlockDesc* bd = P.d_blk + P.blk_first[s];
+      if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
+        Error e = launch_stage_mfma(P, s, prec, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1],
+                                    buf[s & 1], P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
+        if (e.st != MBF_OK) return e;
+      } else {
+        hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W,
+                           buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s], ni, sc);
+      }
+    }
+    if (P.n_vleaf > 0)
+      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf,
+                         reinterpret_cast<const C*>(pd.V0), P.d_vidx, buf[0], P.ld[0],
+                         reinterpret_cast<C*>(out), ldout, ni, 0);
+  }
+  return hip_check("apply launch");
+}
+
+template <typename T>
+Error run_center(const DevFactor& F, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
+                 void* out, int64_t ldout, void* ws, bool accumulate, hipStream_t st) {
+  using C = typename cx<T>::t;
+  const C* KC = reinterpret_cast<const C*>(F.center[prec].center);
+  const int32_t nc = (int32_t)F.n_center;
+  const int ni = (int)nrhs;
+  if (!adj) {
+    hipLaunchKernelGGL(k_center_fwd<T>, dim3((unsigned)((F.nx + 63) / 64), ntiles(nrhs)), dim3(256), 0,
+                       st, KC, F.d_center_idx, F.nx, nc, reinterpret_cast<const C*>(in), ldin,
+                       reinterpret_cast<C*>(out), ldout, ni, accumulate ? 1 : 0);
+  } else {
+    const int nchunk = (int)((F.nx + 4095) / 4096);
+    C* part = reinterpret_cast<C*>(ws);
+    hipLaunchKernelGGL(k_center_adj_partial<T>, dim3(nchunk, (nc + 63) / 64, (unsigned)((nrhs + 3) / 4)),
+                       dim3(256), 0, st, KC, F.nx, nc, reinterpret_cast<const C*>(in), ldin, ni, part);
+    hipLaunchKernelGGL(k_center_adj_reduce<T>, dim3((unsigned)(((int64_t)nc * nrhs + 255) / 256)),
+                       dim3(256), 0, st, part, nchunk, nc, F.d_center_idx, reinterpret_cast<C*>(out),
+                       ldout, ni);
+  }
+  return hip_check("center launch");
+}
+
+int64_t state_ld_max(const DevFactor& F) {
+  int64_t mx = 4;
+  for (auto& P : F.parts)
+    for (auto v : P.ld) mx = std::max(mx, v);
+  return mx;
+}
+
+}  // namespace
+
+size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs) {
+  const size_t es = prec == MBF_C128 ? 16 : 8;
+  size_t b = 2 * (size_t)state_ld_max(F) * (size_t)nrhs * es;
+  if (F.n_center > 0) {
+    const size_t nchunk = (size_t)((F.nx + 4095) / 4096);
+    b = std::max(b, nchunk * (size_t)F.n_center * (size_t)nrhs * es);
+  }
+  return (b + 255) / 256 * 256;
+}
+
+Error launch_apply(const DevFactor& F, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
+                   void* out, int64_t ldout, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (nrhs <= 0) return {MBF_OK, ""};
+  if (ws_bytes < workspace_bytes(F, prec, nrhs)) return {MBF_ERR_INVALID_ARG, "workspace too small"};
+  const int64_t ws_ld = state_ld_max(F);
+  bool acc = false;
+  if (F.n_center > 0 && !adj) {
+    Error e = prec == MBF_C128 ? run_center<double>(F, prec, adj, nrhs, in, ldin, out, ldout, ws, false, st)
+                               : run_center<float>(F, prec, adj, nrhs, in, ldin, out, ldout, ws, false, st);
+    if (e.st != MBF_OK) return e;
+    acc = true;
+  }
+  for (const auto& P : F.parts) {
+    Error e = prec == MBF_C128
+                  ? run_part<double>(P, prec, adj, nrhs, in, ldin, out, ldout, ws, ws_ld, acc && !adj, st)
+                  : run_part<float>(P, prec, adj, nrhs, in, ldin, out, ldout, ws, ws_ld, acc && !adj, st);
+    if (e.st != MBF_OK) return e;
+    acc = true;
+  }
+  if (F.n_center > 0 && adj) {
+    Error e = prec == MBF_C128 ? run_center<double>(F, prec, adj, nrhs, in, ldin, out, ldout, ws, false, st)
+                               : run_center<float>(F, prec, adj, nrhs, in, ldin, out, ldout, ws, false, st);
+    if (e.st != MBF_OK) return e;
+  }
+  return {MBF_OK, ""};
+}
+
+}  // namespace mbf

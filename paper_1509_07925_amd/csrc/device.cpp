@@ -1,0 +1,284 @@
+// Upload of host factorizations to HBM in the apply layout (see device.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "device.h"
+
+namespace mbf {
+
+namespace {
+
+struct bf16x4 {
+  uint16_t v[4];
+};
+
+template <typename T>
+Error dev_alloc_copy(void** dst, const T* src, size_t count, size_t& bytes) {
+  *dst = nullptr;
+  if (count == 0) return {MBF_OK, ""};
+  size_t nb = count * sizeof(T);
+  hipError_t e = hipMalloc(dst, nb);
+  if (e != hipSuccess) {
+    *dst = nullptr;
+    return {e == hipErrorOutOfMemory ? MBF_ERR_OOM : MBF_ERR_HIP,
+            std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+  }
+  e = hipMemcpy(*dst, src, nb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return {MBF_ERR_HIP, std::string("hipMemcpy failed: ") + hipGetErrorString(e)};
+  bytes += nb;
+  return {MBF_OK, ""};
+}
+
+// Round-to-nearest-even FP32 -> BF16 (bit manipulation; NaN kept quiet).
+inline uint16_t f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+inline float bf2f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Convert complex128 data to the storage type of precision p.
+Error upload_complex(int p, const cd* src, size_t count, void** dst, size_t& bytes) {
+  if (p == MBF_C128) return dev_alloc_copy(dst, reinterpret_cast<const double*>(src), 2 * count, bytes);
+  std::vector<float> tmp(2 * count);
+  for (size_t i = 0; i < count; ++i) {
+    tmp[2 * i] = (float)src[i].real();
+    tmp[2 * i + 1] = (float)src[i].imag();
+  }
+  return dev_alloc_copy(dst, tmp.data(), tmp.size(), bytes);
+}
+
+// Stage blocks for the split-BF16 path: per complex entry (re_hi, im_hi,
+// re_lo, im_lo) with hi = bf16(x), lo = bf16(x - hi).
+Error upload_split(const cd* src, size_t count, void** dst, size_t& bytes) {
+  std::vector<bf16x4> tmp(count);
+  for (size_t i = 0; i < count; ++i) {
+    float re = (float)src[i].real(), im = (float)src[i].imag();
+    uint16_t rh = f2bf(re), ih = f2bf(im);
+    tmp[i].v[0] = rh;
+    tmp[i].v[1] = ih;
+    tmp[i].v[2] = f2bf(re - bf2f(rh));
+    tmp[i].v[3] = f2bf(im - bf2f(ih));
+  }
+  return dev_alloc_copy(dst, tmp.data(), tmp.size(), bytes);
+}
+
+Error upload_real(int p, const double* src, size_t count, void** dst, size_t& bytes) {
+  if (p == MBF_C128) return dev_alloc_copy(dst, src, count, bytes);
+  std::vector<float> tmp(count);
+  for (size_t i = 0; i < count; ++i) tmp[i] = (float)src[i];
+  return dev_alloc_copy(dst, tmp.data(), count, bytes);
+}
+
+#define MBF_TRY(expr)                   \
+  do {                                  \
+    Error _e = (expr);                  \
+    if (_e.st != MBF_OK) return _e;     \
+  } while (0)
+
+}  // namespace
+
+Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mask, DevPart& P) {
+  const int L = f.L;
+  const Tree& xt = f.xt;
+  const Tree& ot = f.ot;
+  P.L = L;
+  P.m = f.m;
+  P.nx = xt.npts;
+  P.nxi = ot.npts;
+  std::vector<std::vector<int64_t>> roff(L + 1);
+  P.rows.assign(L + 1, 0);
+  P.ld.assign(L + 1, 0);
+  P.max_rank.assign(L + 1, 0);
+  for (int s = 0; s <= L; ++s) {
+    const auto& rk = f.rank[s];
+    roff[s].resize(rk.size() + 1);
+    int64_t acc = 0;
+    for (size_t p = 0; p < rk.size(); ++p) {
+      roff[s][p] = acc;
+      acc += rk[p];
+      P.max_rank[s] = std::max(P.max_rank[s], rk[p]);
+    }
+    roff[s][rk.size()] = acc;
+    if (acc > INT32_MAX) return {MBF_ERR_UNSUPPORTED, "stage state exceeds 2^31 rows"};
+    P.rows[s] = acc;
+    P.ld[s] = std::max<int64_t>(4, (acc + 3) / 4 * 4);
+  }
+  // Stage block descriptors.
+  std::vector<BlockDesc> blks;
+  P.nblk.assign(L, 0);
+  P.blk_first.assign(L, 0);
+  P.w_stage_off.assign(L, 0);
+  P.max_M.assign(L, 0);
+  P.max_K.assign(L, 0);
+  int64_t woff = 0;
+  for (int s = 0; s < L; ++s) {
+    const int lo = L - s - 1;
+    P.blk_first[s] = (int64_t)blks.size();
+    P.w_stage_off[s] = woff;
+    int64_t b = 0;
+    for (int32_t ia = 0; ia < xt.nn(s); ++ia)
+      for (int32_t ibp = 0; ibp < ot.nn(lo); ++ibp, ++b) {
+        BlockDesc d{};
+        d.w_off = woff + f.Woff[s][b];
+        const int32_t ib0 = ot.cfirst[lo][ibp], ib1 = ot.cfirst[lo][ibp + 1];
+        d.in_row = (int32_t)roff[s][f.pair(s, ia, ib0)];
+        d.K = (int32_t)(roff[s][f.pair(s, ia, ib1 - 1) + 1] - d.in_row);
+        int32_t M = 0, t = 0;
+        for (int32_t it = xt.cfirst[s][ia]; it < xt.cfirst[s][ia + 1]; ++it, ++t) {
+          const int64_t p = f.pair(s + 1, it, ibp);
+          d.ms[t] = M;
+          d.orow[t] = (int32_t)roff[s + 1][p];
+          M += f.rank[s + 1][p];
+        }
+        for (; t < 4; ++t) {
+          d.ms[t] = M;
+          d.orow[t] = 0;
+        }
+        d.M = M;
+        if ((int64_t)d.M * d.K != f.Woff[s][b + 1] - f.Woff[s][b])
+          return {MBF_ERR_INVALID_ARG, "block size mismatch at stage " + std::to_string(s)};
+        P.max_M[s] = std::max(P.max_M[s], d.M);
+        P.max_K[s] = std::max(P.max_K[s], d.K);
+        blks.push_back(d);
+      }
+    P.nblk[s] = b;
+    woff += (int64_t)f.W[s].size();
+  }
+  P.w_elems = woff;
+  // Leaves.
+  std::vector<LeafDesc> vl, ul;
+  int64_t fo = 0;
+  for (int32_t ib = 0; ib < ot.nn(L); ++ib) {
+    LeafDesc d{};
+    d.f_off = fo;
+    d.p_off = (int32_t)ot.off[L][ib];
+    d.np = (int32_t)ot.size(L, ib);
+    d.r = f.rank[0][f.pair(0, 0, ib)];
+    d.row = (int32_t)roff[0][f.pair(0, 0, ib)];
+    if ((int64_t)d.np * d.r != (int64_t)f.V0[ib].size())
+      return {MBF_ERR_INVALID_ARG, "Omega leaf factor size mismatch"};
+    fo += (int64_t)d.np * d.r;
+    P.max_vnp = std::max(P.max_vnp, d.np);
+    P.max_vr = std::max(P.max_vr, d.r);
+    vl.push_back(d);
+  }
+  P.v_elems = fo;
+  fo = 0;
+  for (int32_t ia = 0; ia < xt.nn(L); ++ia) {
+    LeafDesc d{};
+    d.f_off = fo;
+    d.p_off = (int32_t)xt.off[L][ia];
+    d.np = (int32_t)xt.size(L, ia);
+    d.r = f.rank[L][f.pair(L, ia, 0)];
+    d.row = (int32_t)roff[L][f.pair(L, ia, 0)];
+    if ((int64_t)d.np * d.r != (int64_t)f.UL[ia].size())
+      return {MBF_ERR_INVALID_ARG, "X leaf factor size mismatch"};
+    fo += (int64_t)d.np * d.r;
+    P.max_unp = std::max(P.max_unp, d.np);
+    P.max_ur = std::max(P.max_ur, d.r);
+    ul.push_back(d);
+  }
+  P.u_elems = fo;
+  P.n_vleaf = (int32_t)vl.size();
+  P.n_uleaf = (int32_t)ul.size();
+  if ((int64_t)f.S.size() != P.rows[f.m]) return {MBF_ERR_INVALID_ARG, "middle scaling size mismatch"};
+  P.s_elems = (int64_t)f.S.size();
+  P.nnz = host_nnz(f);
+
+  std::vector<int32_t> vidx(ot.npts), uidx(xt.npts);
+  for (int64_t i = 0; i < ot.npts; ++i) vidx[i] = (int32_t)(idx_map ? idx_map[ot.perm[i]] : ot.perm[i]);
+  for (int64_t i = 0; i < xt.npts; ++i) uidx[i] = (int32_t)xt.perm[i];
+
+  size_t meta = 0;
+  MBF_TRY(dev_alloc_copy((void**)&P.d_blk, blks.data(), blks.size(), meta));
+  MBF_TRY(dev_alloc_copy((void**)&P.d_vleaf, vl.data(), vl.size(), meta));
+  MBF_TRY(dev_alloc_copy((void**)&P.d_uleaf, ul.data(), ul.size(), meta));
+  MBF_TRY(dev_alloc_copy((void**)&P.d_vidx, vidx.data(), vidx.size(), meta));
+  MBF_TRY(dev_alloc_copy((void**)&P.d_uidx, uidx.data(), uidx.size(), meta));
+
+  // Concatenate host blocks once per upload.
+  std::vector<cd> Wall((size_t)woff), Vall((size_t)P.v_elems), Uall((size_t)P.u_elems);
+  {
+    size_t o = 0;
+    for (int s = 0; s < L; ++s) {
+      std::copy(f.W[s].begin(), f.W[s].end(), Wall.begin() + o);
+      o += f.W[s].size();
+    }
+    o = 0;
+    for (auto& v : f.V0) {
+      std::copy(v.begin(), v.end(), Vall.begin() + o);
+      o += v.size();
+    }
+    o = 0;
+    for (auto& v : f.UL) {
+      std::copy(v.begin(), v.end(), Uall.begin() + o);
+      o += v.size();
+    }
+  }
+  for (int p = 0; p < kNumPrec; ++p) {
+    if (!(prec_mask & (1u << p))) continue;
+    PrecData& d = P.prec[p];
+    d.present = true;
+    const int leafp = (p == MBF_C128) ? MBF_C128 : MBF_C64;
+    if (p == MBF_C64_SPLIT_BF16)
+      MBF_TRY(upload_split(Wall.data(), Wall.size(), &d.W, d.bytes));
+    else
+      MBF_TRY(upload_complex(p, Wall.data(), Wall.size(), &d.W, d.bytes));
+    MBF_TRY(upload_complex(leafp, Vall.data(), Vall.size(), &d.V0, d.bytes));
+    MBF_TRY(upload_complex(leafp, Uall.data(), Uall.size(), &d.UL, d.bytes));
+    MBF_TRY(upload_real(leafp, f.S.data(), f.S.size(), &d.S, d.bytes));
+  }
+  return {MBF_OK, ""};
+}
+
+Error upload_center(DevFactor& F, const std::vector<cd>& KC, const std::vector<int64_t>& idx,
+                    uint32_t prec_mask) {
+  F.n_center = (int64_t)idx.size();
+  std::vector<int32_t> ci(idx.begin(), idx.end());
+  size_t meta = 0;
+  MBF_TRY(dev_alloc_copy((void**)&F.d_center_idx, ci.data(), ci.size(), meta));
+  for (int p = 0; p < kNumPrec; ++p) {
+    if (!(prec_mask & (1u << p))) continue;
+    PrecData& d = F.center[p];
+    d.present = true;
+    MBF_TRY(upload_complex(p == MBF_C128 ? MBF_C128 : MBF_C64, KC.data(), KC.size(), &d.center, d.bytes));
+  }
+  return {MBF_OK, ""};
+}
+
+static void free_prec(PrecData& d) {
+  (void)hipFree(d.W);
+  (void)hipFree(d.V0);
+  (void)hipFree(d.UL);
+  (void)hipFree(d.S);
+  (void)hipFree(d.center);
+  d = PrecData{};
+}
+
+void free_factor(DevFactor& F) {
+  for (auto& P : F.parts) {
+    (void)hipFree(P.d_blk);
+    (void)hipFree(P.d_vleaf);
+    (void)hipFree(P.d_uleaf);
+    (void)hipFree(P.d_vidx);
+    (void)hipFree(P.d_uidx);
+    for (auto& d : P.prec) free_prec(d);
+  }
+  F.parts.clear();
+  (void)hipFree(F.d_center_idx);
+  F.d_center_idx = nullptr;
+  for (auto& d : F.center) free_prec(d);
+}
+
+}  // namespace mbf

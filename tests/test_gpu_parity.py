@@ -1,0 +1,175 @@
+"""GPU parity: the HIP apply against the FP64 oracle (needs an MI355X).
+
+Arithmetic parity: the oracle builds a factorization, the library imports
+the same factors (mbf_import), and both apply them to the same seeded
+vectors.  Bars (relative l2 error over all outputs):
+  complex128 path  <= 1e-12
+  complex64 path   <= 1e-6    (FP32 apply vs FP64 oracle)
+End-to-end: the library's own build (mbf_build) applied on the GPU against
+the plain definition (FFT closed form / direct sum), within 10 x tol.
+"""
+
+import numpy as np
+import pytest
+
+import mbf_workloads as W
+from oracle import butterfly, direct, kernels
+from tests.factor_io import to_import
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BAR = {"c128": 1e-12, "c64": 1e-6}
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _mbf():
+    import paper_1509_07925_amd as mbf
+    return mbf
+
+
+def _to_gpu(a, prec):
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to(_dev(), dt)
+    return t.t()  # column-major view (N, nrhs)
+
+
+def _from_gpu(t):
+    torch.cuda.synchronize()
+    return t.t().contiguous().cpu().numpy().astype(np.complex128).T
+
+
+def _dft_oracle(n, leaf, tol, method="exact"):
+    x, xi = W.grid_x_integer(n), W.grid_omega(n)
+    L = int(np.log2(n // leaf))
+    return butterfly.build_plain(kernels.dft(n), x, xi, ((0, 0), n), ((-n / 2, -n / 2), n), L, tol,
+                                 10 ** 6, method=method)
+
+
+def _import(bf, precs):
+    return _mbf().Factor.import_factors(precs=precs, **to_import(bf))
+
+
+def _check_both(F, bf, nx, nxi, nrhs, prec, seed=0):
+    g = W.rhs(nxi, nrhs, seed=seed)
+    u = _from_gpu(F.apply(_to_gpu(g, prec), prec=prec))
+    assert direct.rel_err(u, bf.apply(g)) <= BAR[prec]
+    h = W.rhs(nx, nrhs, seed=seed + 1)
+    v = _from_gpu(F.apply_adjoint(_to_gpu(h, prec), prec=prec))
+    assert direct.rel_err(v, bf.adjoint(h)) <= BAR[prec]
+    return u, v
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [1, 3, 37])
+def test_dft_small_import_parity(prec, nrhs):
+    n = 16
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, [prec])
+    _check_both(F, bf, n * n, n * n, nrhs, prec)
+
+
+@pytest.mark.parametrize("leaf,tol", [(1, 1e-14), (4, 1e-14), (2, 1e-5)])
+def test_dft_depth_variants_parity(leaf, tol):
+    # odd and even depth, middle level 0 and > 0, full rank and truncated
+    n = 16
+    bf = _dft_oracle(n, leaf, tol)
+    F = _import(bf, ["c128", "c64"])
+    for prec in ("c128", "c64"):
+        _check_both(F, bf, n * n, n * n, 5, prec)
+
+
+def test_dft_n64_correctness_config():
+    """2D DFT, n = 64, 8 x 8 leaves, tol 1e-8, one complex128 RHS (FP64 apply)."""
+    n = 64
+    bf = _dft_oracle(n, 8, 1e-8)
+    F = _import(bf, ["c128", "c64"])
+    u, _ = _check_both(F, bf, n * n, n * n, 1, "c128")
+    g = W.rhs(n * n, 1, seed=0)
+    assert direct.rel_err(u, direct.dft_fft(n, g)) < 1e-7
+    _check_both(F, bf, n * n, n * n, 64, "c64")
+
+
+def test_polar_fio_ragged_parity():
+    n = 32
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    bf = butterfly.build_polar(kernels.fio_radon(n), x, xi, n, ((0, 0), 1.0), 4, 1e-6, 10 ** 6)
+    F = _import(bf, ["c64", "c128"])
+    _check_both(F, bf, n * n, n * n, 33, "c64")
+    _check_both(F, bf, n * n, n * n, 2, "c128")
+
+
+def test_multiscale_fio_parity():
+    mbf = _mbf()
+    n = 64
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    ms = butterfly.build_multiscale(kernels.fio_radon(n), x, xi, n, ((0, 0), 1.0), 1e-6, 10 ** 6, leaf_side=4)
+    parts = [_import(bf, ["c64"]) for _, _, bf in ms.parts]
+    F = mbf.multiscale_assemble(parts, [idx for _, idx, _ in ms.parts], n * n, ms.center_idx, ms.KC,
+                                precs=["c64"])
+    _check_both(F, ms, n * n, n * n, 16, "c64")
+
+
+def test_batch_columns_equal_solo_apply():
+    n = 16
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, ["c64"])
+    g = W.rhs(n * n, 40, seed=3)
+    ub = _from_gpu(F.apply(_to_gpu(g, "c64")))
+    for j in (0, 17, 39):
+        uj = _from_gpu(F.apply(_to_gpu(g[:, j:j + 1], "c64")))
+        np.testing.assert_array_equal(ub[:, j:j + 1], uj)
+
+
+@pytest.mark.parametrize("n,leaf,tol", [(32, 2, 1e-6), (64, 4, 1e-6)])
+def test_library_build_dft_end_to_end(n, leaf, tol):
+    mbf = _mbf()
+    x, xi = W.grid_x_integer(n), W.grid_omega(n)
+    F = mbf.Factor.build(x, xi, n, kernel="dft", tol=tol, leaf_side=leaf, precs=["c64", "c128"])
+    g = W.rhs(n * n, 8, seed=5)
+    ref = direct.dft_fft(n, g)
+    u = _from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128"))
+    assert direct.rel_err(u, ref) < 10 * tol
+    u32 = _from_gpu(F.apply(_to_gpu(g, "c64")))
+    assert direct.rel_err(u32, ref) < 10 * tol + 1e-6
+    h = W.rhs(n * n, 8, seed=6)
+    v = _from_gpu(F.apply_adjoint(_to_gpu(h, "c128"), prec="c128"))
+    assert direct.rel_err(v, direct.dft_fft_adjoint(n, h)) < 10 * tol
+    # adjoint identity of the factorized operator
+    lhs = np.vdot(h, u)
+    rhs = np.vdot(v, g)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+@pytest.mark.parametrize("split", ["polar", "multiscale"])
+def test_library_build_fio_splits_end_to_end(split):
+    mbf = _mbf()
+    n = 64
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    kw = dict(depth=4) if split == "polar" else dict(leaf_side=4)
+    F = mbf.Factor.build(x, xi, n, kernel="fio", tol=1e-6, split=split, precs=["c64"], **kw)
+    g = W.rhs(n * n, 4, seed=7)
+    rows = W.sample_rows(n * n, 256, seed=0)
+    ref = direct.direct_rows(kernels.fio_radon(n), x, xi, g, rows)
+    u = _from_gpu(F.apply(_to_gpu(g, "c64")))
+    assert direct.rel_err(u[rows], ref) < 1e-4
+    h = W.rhs(n * n, 4, seed=8)
+    v = _from_gpu(F.apply_adjoint(_to_gpu(h, "c64")))
+    lhs, rhs = np.vdot(h, u), np.vdot(v, g)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_library_build_linear_phase_closed_form():
+    mbf = _mbf()
+    n = 64
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    F = mbf.Factor.build(x, xi, n, kernel="fio", c_scale=0.0, tol=1e-7, split="multiscale",
+                         leaf_side=4, precs=["c128"])
+    g = W.rhs(n * n, 2, seed=9)
+    u = _from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128"))
+    assert direct.rel_err(u, direct.linear_phase_ifft(n, g)) < 1e-5
