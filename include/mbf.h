@@ -225,6 +225,31 @@ typedef struct {
 } mbf_info_t;
 mbf_status mbf_info(mbf_factor f, mbf_info_t* out);
 
+/* Per-launch timing of the apply kernels with HIP events (instrumentation,
+ * Section 2.5: cost per factor).  mbf_profile_begin creates 2 * max_launches
+ * events (it may allocate; call it outside graph capture and timed loops).
+ * While active, every kernel that mbf_apply / mbf_apply_adjoint enqueues
+ * records an event pair on its stream, until max_launches are used.
+ * mbf_profile_end waits for those events, writes up to `cap` records and
+ * the number of records to *count, and stops profiling.
+ *   kind:  0 leaf project, 1 stage block product, 2 leaf reconstruct,
+ *          3 dense center (multiscale)
+ *   flops: algorithmic real flops of the launch (8 per complex multiply-add
+ *          of a factor entry with one vector entry)
+ *   bytes: algorithmic HBM bytes (factor entries read once + vectors read
+ *          and written once) */
+typedef struct {
+  int32_t kind;
+  int32_t part;
+  int32_t stage;
+  int32_t prec;
+  double ms;
+  double flops;
+  double bytes;
+} mbf_launch_record;
+mbf_status mbf_profile_begin(mbf_factor f, int32_t max_launches);
+mbf_status mbf_profile_end(mbf_factor f, mbf_launch_record* out, int32_t cap, int32_t* count);
+
 void mbf_destroy(mbf_factor f);
 const char* mbf_last_error(void);
 

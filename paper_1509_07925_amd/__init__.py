@@ -56,12 +56,18 @@ class Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t)]
 
 
+class LaunchRecord(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("part", ctypes.c_int32), ("stage", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 ENTRY_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double))
 
 EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
-           "mbf_kernel_fio"]
+           "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end"]
 
 
 def lib():
@@ -82,11 +88,13 @@ def lib():
     L.mbf_apply.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
     L.mbf_apply_adjoint.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
     L.mbf_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.mbf_profile_begin.argtypes = [vp, i32]
+    L.mbf_profile_end.argtypes = [vp, ctypes.POINTER(LaunchRecord), i32, ctypes.POINTER(i32)]
     L.mbf_destroy.argtypes = [vp]
     L.mbf_destroy.restype = None
     L.mbf_last_error.restype = ctypes.c_char_p
     for name in ("mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
-                 "mbf_apply_adjoint", "mbf_info"):
+                 "mbf_apply_adjoint", "mbf_info", "mbf_profile_begin", "mbf_profile_end"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -230,6 +238,17 @@ class Factor:
     def apply_adjoint(self, h, out=None, prec="c64", workspace=None, stream=None):
         """v = K^* h (mbf_apply_adjoint)."""
         return self._run(True, h, out, prec, workspace, stream)
+
+    def profile_begin(self, max_launches):
+        _check(lib().mbf_profile_begin(self._h, max_launches))
+
+    def profile_end(self, cap=1 << 16):
+        """Per-launch records (kind, part, stage, prec, ms, flops, bytes) as dicts."""
+        buf = (LaunchRecord * cap)()
+        n = ctypes.c_int32()
+        _check(lib().mbf_profile_end(self._h, buf, cap, ctypes.byref(n)))
+        return [dict(kind=r.kind, part=r.part, stage=r.stage, prec=r.prec, ms=r.ms, flops=r.flops,
+                     bytes=r.bytes) for r in buf[:n.value]]
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -391,9 +391,32 @@ inline Error hip_check(const char* what) {
 
 inline unsigned ntiles(int64_t nrhs) { return (unsigned)((nrhs + kTN - 1) / kTN); }
 
+// Event pair around one launch when profiling is active.
+struct Timed {
+  Profiler* pr;
+  hipStream_t st;
+  int idx = -1;
+  Timed(Profiler* p, hipStream_t s, int kind, int part, int stage, int prec, double flops, double bytes)
+      : pr(p), st(s) {
+    if (!pr || !pr->on || pr->used >= pr->cap) return;
+    idx = pr->used++;
+    pr->rec[idx] = mbf_launch_record{kind, part, stage, prec, 0.0, flops, bytes};
+    (void)hipEventRecord(pr->ev[2 * idx], st);
+  }
+  ~Timed() {
+    if (idx >= 0) (void)hipEventRecord(pr->ev[2 * idx + 1], st);
+  }
+};
+
+inline int64_t stage_nnz(const DevPart& P, int s) {
+  const int64_t e = (s + 1 < P.L) ? P.w_stage_off[s + 1] : P.w_elems;
+  return e - P.w_stage_off[s];
+}
+
 template <typename T>
-Error run_part(const DevPart& P, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
-               void* out, int64_t ldout, void* ws, int64_t ws_ld, bool accumulate, hipStream_t st) {
+Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int64_t nrhs, const void* in,
+               int64_t ldin, void* out, int64_t ldout, void* ws, int64_t ws_ld, bool accumulate,
+               hipStream_t st) {
   using C = typename cx<T>::t;
   const PrecData& pd = P.prec[prec];
   C* buf[2] = {reinterpret_cast<C*>(ws), reinterpret_cast<C*>(ws) + ws_ld * nrhs};
@@ -402,50 +425,68 @@ Error run_part(const DevPart& P, int prec, bool adj, int64_t nrhs, const void* i
   const int L = P.L, m = P.m;
   const unsigned nt = ntiles(nrhs);
   const int ni = (int)nrhs;
+  const double es = sizeof(C), ef = (prec == MBF_C128) ? 16.0 : 8.0, nr = (double)nrhs;
+  auto stage_cost = [&](int s, double& fl, double& by) {
+    const double z = (double)stage_nnz(P, s);
+    fl = 8.0 * z * nr;
+    by = z * ef + (double)(P.rows[s] + P.rows[s + 1]) * nr * es;
+  };
+  const C* Vf = reinterpret_cast<const C*>(pd.V0);
+  const C* Uf = reinterpret_cast<const C*>(pd.UL);
   if (!adj) {
-    if (P.n_vleaf > 0)
-      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf,
-                         reinterpret_cast<const C*>(pd.V0), P.d_vidx, reinterpret_cast<const C*>(in),
-                         ldin, buf[0], P.ld[0], ni, m == 0 ? S : nullptr);
+    if (P.n_vleaf > 0) {
+      Timed t(pr, st, 0, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
+      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf, Vf, P.d_vidx,
+                         reinterpret_cast<const C*>(in), ldin, buf[0], P.ld[0], ni, m == 0 ? S : nullptr);
+    }
     for (int s = 0; s < L; ++s) {
       if (P.nblk[s] == 0) continue;
       const T* sc = (s == m - 1) ? S : nullptr;
       const BlockDesc* bd = P.d_blk + P.blk_first[s];
+      double fl, by;
+      stage_cost(s, fl, by);
+      Timed t(pr, st, 1, pidx, s, prec, fl, by);
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
         Error e = launch_stage_mfma(P, s, prec, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1],
                                     P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
-        hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W,
-                           buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni, sc);
+        hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[s & 1],
+                           P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni, sc);
       }
     }
-    if (P.n_uleaf > 0)
-      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf,
-                         reinterpret_cast<const C*>(pd.UL), P.d_uidx, buf[L & 1], P.ld[L],
-                         reinterpret_cast<C*>(out), ldout, ni, accumulate ? 1 : 0);
+    if (P.n_uleaf > 0) {
+      Timed t(pr, st, 2, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
+      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf, Uf, P.d_uidx,
+                         buf[L & 1], P.ld[L], reinterpret_cast<C*>(out), ldout, ni, accumulate ? 1 : 0);
+    }
   } else {
-    if (P.n_uleaf > 0)
-      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf,
-                         reinterpret_cast<const C*>(pd.UL), P.d_uidx, reinterpret_cast<const C*>(in),
-                         ldin, buf[L & 1], P.ld[L], ni, m == L ? S : nullptr);
+    if (P.n_uleaf > 0) {
+      Timed t(pr, st, 0, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
+      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf, Uf, P.d_uidx,
+                         reinterpret_cast<const C*>(in), ldin, buf[L & 1], P.ld[L], ni, m == L ? S : nullptr);
+    }
     for (int s = L - 1; s >= 0; --s) {
       if (P.nblk[s] == 0) continue;
       const T* sc = (s == m) ? S : nullptr;
       const BlockDesc* bd = P.d_blk + P.blk_first[s];
+      double fl, by;
+      stage_cost(s, fl, by);
+      Timed t(pr, st, 1, pidx, s, prec, fl, by);
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
-        Error e = launch_stage_mfma(P, s, prec, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1],
-                                    buf[s & 1], P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
+        Error e = launch_stage_mfma(P, s, prec, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
+                                    P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
-        hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W,
-                           buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s], ni, sc);
+        hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[(s + 1) & 1],
+                           P.ld[s + 1], buf[s & 1], P.ld[s], ni, sc);
       }
     }
-    if (P.n_vleaf > 0)
-      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf,
-                         reinterpret_cast<const C*>(pd.V0), P.d_vidx, buf[0], P.ld[0],
-                         reinterpret_cast<C*>(out), ldout, ni, 0);
+    if (P.n_vleaf > 0) {
+      Timed t(pr, st, 2, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
+      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf, Vf, P.d_vidx,
+                         buf[0], P.ld[0], reinterpret_cast<C*>(out), ldout, ni, 0);
+    }
   }
   return hip_check("apply launch");
 }
@@ -457,6 +498,8 @@ Error run_center(const DevFactor& F, int prec, bool adj, int64_t nrhs, const voi
   const C* KC = reinterpret_cast<const C*>(F.center[prec].center);
   const int32_t nc = (int32_t)F.n_center;
   const int ni = (int)nrhs;
+  const double es = sizeof(C), nr = (double)nrhs, z = (double)F.nx * nc;
+  Timed t(&F.prof, st, 3, -1, 0, prec, 8.0 * z * nr, z * es + (double)(F.nx + nc) * nr * es);
   if (!adj) {
     hipLaunchKernelGGL(k_center_fwd<T>, dim3((unsigned)((F.nx + 63) / 64), ntiles(nrhs)), dim3(256), 0,
                        st, KC, F.d_center_idx, F.nx, nc, reinterpret_cast<const C*>(in), ldin,
@@ -504,10 +547,12 @@ Error launch_apply(const DevFactor& F, int prec, bool adj, int64_t nrhs, const v
     if (e.st != MBF_OK) return e;
     acc = true;
   }
-  for (const auto& P : F.parts) {
-    Error e = prec == MBF_C128
-                  ? run_part<double>(P, prec, adj, nrhs, in, ldin, out, ldout, ws, ws_ld, acc && !adj, st)
-                  : run_part<float>(P, prec, adj, nrhs, in, ldin, out, ldout, ws, ws_ld, acc && !adj, st);
+  for (size_t i = 0; i < F.parts.size(); ++i) {
+    const auto& P = F.parts[i];
+    Error e = prec == MBF_C128 ? run_part<double>(P, (int)i, &F.prof, prec, adj, nrhs, in, ldin, out, ldout, ws,
+                                                  ws_ld, acc && !adj, st)
+                               : run_part<float>(P, (int)i, &F.prof, prec, adj, nrhs, in, ldin, out, ldout, ws,
+                                                 ws_ld, acc && !adj, st);
     if (e.st != MBF_OK) return e;
     acc = true;
   }

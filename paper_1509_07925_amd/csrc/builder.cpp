@@ -15,7 +15,10 @@
 #include "builder.h"
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <map>
@@ -183,6 +186,28 @@ Mat merge_rows(const std::vector<const Mat*>& parts, int64_t r0, int64_t r1) {
   return W;
 }
 
+// Progress lines on stderr when MBF_VERBOSE is set (long builds).
+struct Progress {
+  const char* what;
+  int64_t total;
+  std::atomic<int64_t> done{0};
+  std::mutex mu;
+  std::chrono::steady_clock::time_point last = std::chrono::steady_clock::now();
+  bool on = std::getenv("MBF_VERBOSE") != nullptr;
+  Progress(const char* w, int64_t t) : what(w), total(t) {}
+  void tick() {
+    const int64_t d = ++done;
+    if (!on) return;
+    std::lock_guard<std::mutex> g(mu);
+    auto now = std::chrono::steady_clock::now();
+    if (d == total || std::chrono::duration<double>(now - last).count() > 10.0) {
+      last = now;
+      std::fprintf(stderr, "[mbf build] %s %lld/%lld\n", what, (long long)d, (long long)total);
+      std::fflush(stderr);
+    }
+  }
+};
+
 template <typename F>
 void parallel_for(int64_t n, int threads, F&& fn) {
   std::atomic<int64_t> next{0};
@@ -270,6 +295,7 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   }
 
   // ---------------- U tasks: one per middle-level X node
+  Progress pu("U pass", xt.nn(m)), pv("V pass", ot.nn(L - m));
   parallel_for(xt.nn(m), threads, [&](int64_t ia_m) {
     std::map<std::pair<int32_t, int32_t>, Mat> U;  // (ia, ib) at current stage
     for (int32_t ib = 0; ib < ot.nn(L - m); ++ib) {
@@ -328,6 +354,7 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
       Mat& Uf = U.at({ia, 0});
       f.UL[ia] = std::move(Uf.a);
     }
+    pu.tick();
   });
 
   // ---------------- V tasks: one per middle-level Omega node
@@ -387,6 +414,7 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
       Mat& Vf = V.at({0, ib});
       f.V0[ib] = std::move(Vf.a);
     }
+    pv.tick();
   });
 
   for (size_t p = 0; p < rank_m_v.size(); ++p)

@@ -274,8 +274,54 @@ mbf_status mbf_info(mbf_factor f, mbf_info_t* out) {
   return MBF_OK;
 }
 
+static void profile_release(Profiler& p) {
+  for (auto e : p.ev) (void)hipEventDestroy(e);
+  p = Profiler{};
+}
+
+mbf_status mbf_profile_begin(mbf_factor f, int32_t max_launches) {
+  if (!f || max_launches <= 0 || max_launches > (1 << 20)) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
+  Profiler& p = f->dev.prof;
+  profile_release(p);
+  p.ev.resize(2 * (size_t)max_launches);
+  for (auto& e : p.ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      profile_release(p);
+      return fail(MBF_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(r));
+    }
+  }
+  p.rec.resize(max_launches);
+  p.cap = max_launches;
+  p.used = 0;
+  p.on = true;
+  return MBF_OK;
+}
+
+mbf_status mbf_profile_end(mbf_factor f, mbf_launch_record* out, int32_t cap, int32_t* count) {
+  if (!f || !count || (cap > 0 && !out)) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
+  Profiler& p = f->dev.prof;
+  int32_t n = 0;
+  for (int32_t i = 0; i < p.used; ++i) {
+    hipError_t r = hipEventSynchronize(p.ev[2 * i + 1]);
+    float ms = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]);
+    if (r != hipSuccess) {
+      profile_release(p);
+      return fail(MBF_ERR_HIP, std::string("event timing: ") + hipGetErrorString(r));
+    }
+    p.rec[i].ms = ms;
+    if (n < cap) out[n++] = p.rec[i];
+  }
+  *count = n;
+  profile_release(p);
+  return MBF_OK;
+}
+
 void mbf_destroy(mbf_factor f) {
   if (!f) return;
+  profile_release(f->dev.prof);
   free_factor(f->dev);
   delete f;
 }

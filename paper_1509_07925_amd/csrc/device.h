@@ -71,6 +71,13 @@ struct DevPart {
   PrecData prec[kNumPrec];
 };
 
+struct Profiler {
+  bool on = false;
+  int32_t cap = 0, used = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<mbf_launch_record> rec;
+};
+
 struct DevFactor {
   int64_t nx = 0, nxi = 0;
   uint32_t prec_mask = 0;
@@ -81,6 +88,7 @@ struct DevFactor {
   PrecData center[kNumPrec];
   int64_t nnz = 0;
   size_t device_bytes = 0;
+  mutable Profiler prof;
 };
 
 // Upload a host factorization as one part.  idx_map (optional, nxi

@@ -1,13 +1,329 @@
-// Matrix-core (MFMA) stage kernels; see stage_mfma.h.
+// Matrix-core (MFMA) stage kernels for many right-hand sides; see stage_mfma.h.
+//
+// A stage block computes, for the nrhs columns of the state,
+//   forward: out(n, m) = sum_k W(m, k) x(n, k)        (M x K block)
+//   adjoint: out(n, k) = sum_m conj(W(m, k)) x(n, m)
+// i.e. Out^T = In^T W^T: the right-hand sides run along the MFMA rows, the
+// block's output rows along the MFMA columns, and the complex product is
+// the real product of the embeddings
+//   A(n, 2k+c)      = (Re, Im)_c x(n, k)
+//   B(2k+c, 2m+d)   = [[Wr, Wi], [-Wi, Wr]]_{c,d}   (forward)
+//                     [[Wr, -Wi], [Wi, Wr]]_{c,d}   (adjoint, conj(W))
+// so that D(n, 2m+d) is the real (d=0) / imaginary (d=1) part of out(n, m):
+// output rows are interleaved complex and store coalesced into the state.
+//
+// Tile: 64 right-hand sides x 64 complex output rows per workgroup (4 waves
+// of 32 x 64 real columns), reduction staged through LDS in chunks of 16
+// complex entries.  Two arithmetic modes:
+//   F32    v_mfma_f32_32x32x2_f32, one complex k per instruction;
+//   BF16X3 v_mfma_f32_32x32x16_bf16, eight complex k per instruction; every
+//          operand is split as hi + lo (both BF16) and the product is
+//          hi*hi + hi*lo + lo*hi with FP32 accumulation.
+// Workgroup -> tile mapping is XCD-aware: consecutive logical tiles (the
+// right-hand-side tiles of one output tile, then the output tiles of one
+// block) land on the same XCD so that they share its L2.
 #include "stage_mfma.h"
+
+#include <string>
 
 namespace mbf {
 
-bool use_mfma(const DevPart&, int, int64_t, int prec) { return prec == MBF_C64_SPLIT_BF16; }
+namespace {
 
-Error launch_stage_mfma(const DevPart&, int, int, bool, const BlockDesc*, const void*, const void*,
-                        int64_t, void*, int64_t, int, const float*, hipStream_t) {
-  return {MBF_ERR_UNSUPPORTED, "split-BF16 stage kernel not available"};
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TN = 64;   // right-hand sides per tile
+constexpr int TM = 64;   // complex output rows per tile
+constexpr int KC = 16;   // complex reduction entries per chunk
+constexpr int kXcd = 8;  // XCDs per device
+
+__device__ __forceinline__ int32_t grp_row(const BlockDesc& d, int32_t i) {
+  const int t = (i >= d.ms[1]) + (i >= d.ms[2]) + (i >= d.ms[3]);
+  return d.orow[t] + i - d.ms[t];
+}
+
+__device__ __forceinline__ uint32_t f2bf_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf_bits2f(uint32_t h) { return __uint_as_float(h << 16); }
+// (hi, lo) BF16 split of an FP32 value.
+__device__ __forceinline__ void split_bf(float x, uint32_t& hi, uint32_t& lo) {
+  hi = f2bf_bits(x);
+  lo = f2bf_bits(x - bf_bits2f(hi));
+}
+
+struct Tile {
+  int b, mt, nt;
+};
+
+// Logical tile of this workgroup, or b = -1 when it has none.
+__device__ __forceinline__ Tile map_tile(int64_t total, int mtiles, int ntiles) {
+  const int64_t per = (total + kXcd - 1) / kXcd;
+  const int64_t L = blockIdx.x;
+  const int64_t t = (L % kXcd) * per + L / kXcd;
+  Tile r{-1, 0, 0};
+  if (t >= total) return r;
+  r.nt = (int)(t % ntiles);
+  const int64_t rest = t / ntiles;
+  r.mt = (int)(rest % mtiles);
+  r.b = (int)(rest / mtiles);
+  return r;
+}
+
+template <bool ADJ>
+__device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int n0, const v16f* acc, int nacc,
+                                          int wn, int wm, float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                          const float* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  float* o = reinterpret_cast<float*>(out);
+  for (int i = 0; i < nacc; ++i) {
+    const int col = wm + i * 32 + (lane & 31);  // real output column
+    const int m = r0 + (col >> 1);
+    if (m >= R) continue;
+    const int32_t row = ADJ ? d.in_row + m : grp_row(d, m);
+    const float s = scale ? scale[row] : 1.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int n = n0 + wn + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+      if (n < nrhs) o[2 * ((int64_t)n * ld_out + row) + (col & 1)] = acc[i][j] * s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP32
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__ blk,
+                                                   const float2* __restrict__ W,
+                                                   const float2* __restrict__ in, int64_t ld_in,
+                                                   float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                   const float* __restrict__ scale, int mtiles, int ntiles,
+                                                   int64_t total) {
+  constexpr int PA = KC + 4, PB = KC + 4;
+  __shared__ __attribute__((aligned(16))) float As[2][TN][PA];      // [re|im][n][k]
+  __shared__ __attribute__((aligned(16))) float Bs[2][2 * TM][PB];  // [c][real col][k]
+  const Tile tl = map_tile(total, mtiles, ntiles);
+  if (tl.b < 0) return;
+  const BlockDesc d = blk[tl.b];
+  const int R = ADJ ? d.K : d.M;
+  const int Q = ADJ ? d.M : d.K;
+  const int r0 = tl.mt * TM;
+  if (r0 >= R) return;
+  const int n0 = tl.nt * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
+  const float2* Wb = W + d.w_off;
+  v16f acc[2];
+  acc[0] = v16f{};
+  acc[1] = v16f{};
+  for (int q0 = 0; q0 < Q; q0 += KC) {
+    {  // A: 64 right-hand sides x 16 complex reduction entries
+      const int n = tid >> 2, kq = (tid & 3) * 4;
+      const int gn = n0 + n;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = q0 + kq + j;
+        float2 v = make_float2(0.f, 0.f);
+        if (gn < nrhs && q < Q) {
+          const int32_t row = ADJ ? grp_row(d, q) : d.in_row + q;
+          v = in[(int64_t)gn * ld_in + row];
+        }
+        As[0][n][kq + j] = v.x;
+        As[1][n][kq + j] = v.y;
+      }
+    }
+    if (!ADJ) {  // B from W(m, k): 16 k x 64 m, m contiguous in memory
+      const int k = tid >> 4, mq = (tid & 15) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = r0 + mq + j, q = q0 + k;
+        float2 w = make_float2(0.f, 0.f);
+        if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
+        const int c = 2 * (mq + j);
+        Bs[0][c][k] = w.x;
+        Bs[0][c + 1][k] = w.y;
+        Bs[1][c][k] = -w.y;
+        Bs[1][c + 1][k] = w.x;
+      }
+    } else {  // B from conj(W(m', k')): 16 m' (reduction) x 64 k' (output), m' contiguous
+      const int kp = tid >> 2, mq = (tid & 3) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kout = r0 + kp, mr = q0 + mq + j;
+        float2 w = make_float2(0.f, 0.f);
+        if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
+        const int c = 2 * kp;
+        Bs[0][c][mq + j] = w.x;
+        Bs[0][c + 1][mq + j] = -w.y;
+        Bs[1][c][mq + j] = w.y;
+        Bs[1][c + 1][mq + j] = w.x;
+      }
+    }
+    __syncthreads();
+    const int kk = lane >> 5, li = lane & 31;
+#pragma unroll
+    for (int kb = 0; kb < KC; kb += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(&As[kk][wn + li][kb]);
+      const float4 b0 = *reinterpret_cast<const float4*>(&Bs[kk][wm + li][kb]);
+      const float4 b1 = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 + li][kb]);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0.x, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b1.x, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b0.y, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1.y, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b0.z, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b1.z, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b0.w, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b1.w, acc[1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  store_out<ADJ>(d, R, r0, n0, acc, 2, wn, wm, out, ld_out, nrhs, scale);
+}
+
+// ------------------------------------------------------------------ BF16 x3
+// LDS rows hold interleaved pairs along the complex reduction index: entry
+// (row, k) is one 32-bit word = two BF16 values (real-k 2k and 2k+1).
+template <bool ADJ>
+__global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restrict__ blk,
+                                                      const uint2* __restrict__ W,  // (re_hi,im_hi | re_lo,im_lo)
+                                                      const float2* __restrict__ in, int64_t ld_in,
+                                                      float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                      const float* __restrict__ scale, int mtiles, int ntiles,
+                                                      int64_t total) {
+  constexpr int P = KC + 4;  // words per LDS row (16-byte aligned rows)
+  __shared__ __attribute__((aligned(16))) uint32_t Ah[TN][P], Al[TN][P];
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[2 * TM][P], Bl[2 * TM][P];
+  const Tile tl = map_tile(total, mtiles, ntiles);
+  if (tl.b < 0) return;
+  const BlockDesc d = blk[tl.b];
+  const int R = ADJ ? d.K : d.M;
+  const int Q = ADJ ? d.M : d.K;
+  const int r0 = tl.mt * TM;
+  if (r0 >= R) return;
+  const int n0 = tl.nt * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
+  const uint2* Wb = W + d.w_off;
+  v16f acc[2];
+  acc[0] = v16f{};
+  acc[1] = v16f{};
+  for (int q0 = 0; q0 < Q; q0 += KC) {
+    {
+      const int n = tid >> 2, kq = (tid & 3) * 4;
+      const int gn = n0 + n;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = q0 + kq + j;
+        float2 v = make_float2(0.f, 0.f);
+        if (gn < nrhs && q < Q) {
+          const int32_t row = ADJ ? grp_row(d, q) : d.in_row + q;
+          v = in[(int64_t)gn * ld_in + row];
+        }
+        uint32_t rh, rl, ih, il;
+        split_bf(v.x, rh, rl);
+        split_bf(v.y, ih, il);
+        Ah[n][kq + j] = rh | (ih << 16);
+        Al[n][kq + j] = rl | (il << 16);
+      }
+    }
+    if (!ADJ) {
+      const int k = tid >> 4, mq = (tid & 15) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = r0 + mq + j, q = q0 + k;
+        uint2 w = make_uint2(0u, 0u);
+        if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
+        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+        const int c = 2 * (mq + j);
+        // column 2m (real part):      (Wr, -Wi);  column 2m+1 (imag part): (Wi, Wr)
+        Bh[c][k] = reh | ((imh ^ 0x8000u) << 16);
+        Bh[c + 1][k] = imh | (reh << 16);
+        Bl[c][k] = rel | ((iml ^ 0x8000u) << 16);
+        Bl[c + 1][k] = iml | (rel << 16);
+      }
+    } else {
+      const int kp = tid >> 2, mq = (tid & 3) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kout = r0 + kp, mr = q0 + mq + j;
+        uint2 w = make_uint2(0u, 0u);
+        if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
+        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+        const int c = 2 * kp;
+        // conj(W): column 2k' (real part): (Wr, Wi);  column 2k'+1 (imag part): (-Wi, Wr)
+        Bh[c][mq + j] = reh | (imh << 16);
+        Bh[c + 1][mq + j] = (imh ^ 0x8000u) | (reh << 16);
+        Bl[c][mq + j] = rel | (iml << 16);
+        Bl[c + 1][mq + j] = (iml ^ 0x8000u) | (rel << 16);
+      }
+    }
+    __syncthreads();
+    const int kh = lane >> 5, li = lane & 31;
+#pragma unroll
+    for (int kb = 0; kb < KC; kb += 8) {
+      // lane holds real-k 8*kh .. 8*kh+7 of this step = complex k kb + 4*kh .. +3
+      const int ko = kb + 4 * kh;
+      const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[wn + li][ko]));
+      const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[wn + li][ko]));
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[wm + 32 * i + li][ko]));
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[wm + 32 * i + li][ko]));
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  store_out<ADJ>(d, R, r0, n0, acc, 2, wn, wm, out, ld_out, nrhs, scale);
+}
+
+}  // namespace
+
+// FP32: the matrix cores pay off once a block's vectors are reused across
+// enough right-hand sides; below that the generic kernel streams the block.
+bool use_mfma(const DevPart&, int, int64_t nrhs, int prec) {
+  if (prec == MBF_C64_SPLIT_BF16) return true;
+  if (prec == MBF_C64) return nrhs >= 32;
+  return false;
+}
+
+Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const BlockDesc* blk, const void* W,
+                        const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs, const float* scale,
+                        hipStream_t st) {
+  const int Rmax = adj ? P.max_K[s] : P.max_M[s];
+  const int mtiles = std::max(1, (Rmax + TM - 1) / TM);
+  const int ntiles = (nrhs + TN - 1) / TN;
+  const int64_t total = (int64_t)P.nblk[s] * mtiles * ntiles;
+  const int64_t grid = (total + kXcd - 1) / kXcd * kXcd;
+  if (grid > INT32_MAX) return {MBF_ERR_UNSUPPORTED, "stage grid too large"};
+  const float2* x = reinterpret_cast<const float2*>(in);
+  float2* y = reinterpret_cast<float2*>(out);
+  if (prec == MBF_C64) {
+    const float2* w = reinterpret_cast<const float2*>(W);
+    if (adj)
+      hipLaunchKernelGGL(k_stage_f32<true>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y, ld_out,
+                         nrhs, scale, mtiles, ntiles, total);
+    else
+      hipLaunchKernelGGL(k_stage_f32<false>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y, ld_out,
+                         nrhs, scale, mtiles, ntiles, total);
+  } else if (prec == MBF_C64_SPLIT_BF16) {
+    const uint2* w = reinterpret_cast<const uint2*>(W);
+    if (adj)
+      hipLaunchKernelGGL(k_stage_bf16x3<true>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y,
+                         ld_out, nrhs, scale, mtiles, ntiles, total);
+    else
+      hipLaunchKernelGGL(k_stage_bf16x3<false>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y,
+                         ld_out, nrhs, scale, mtiles, ntiles, total);
+  } else {
+    return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel for this precision"};
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return {MBF_ERR_HIP, std::string("stage launch: ") + hipGetErrorString(e)};
+  return {MBF_OK, ""};
 }
 
 }  // namespace mbf

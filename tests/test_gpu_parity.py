@@ -19,7 +19,7 @@ from tests.factor_io import to_import
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-BAR = {"c128": 1e-12, "c64": 1e-6}
+BAR = {"c128": 1e-12, "c64": 1e-6, "bf16x3": 1e-4}
 
 
 def _dev():
@@ -173,3 +173,22 @@ def test_library_build_linear_phase_closed_form():
     g = W.rhs(n * n, 2, seed=9)
     u = _from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128"))
     assert direct.rel_err(u, direct.linear_phase_ifft(n, g)) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["c64", "bf16x3"])
+@pytest.mark.parametrize("n,leaf,tol,nrhs", [(16, 2, 1e-6, 1), (16, 2, 1e-6, 65), (32, 2, 1e-6, 100),
+                                             (16, 4, 1e-14, 32), (32, 8, 1e-8, 64)])
+def test_matrix_core_stage_parity(prec, n, leaf, tol, nrhs):
+    """MFMA stage kernels (FP32, split BF16): several output / RHS tiles, ragged tails."""
+    bf = _dft_oracle(n, leaf, tol)
+    F = _import(bf, [prec])
+    _check_both(F, bf, n * n, n * n, nrhs, prec, seed=nrhs)
+
+
+def test_matrix_core_polar_ragged_bf16x3():
+    n = 32
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    bf = butterfly.build_polar(kernels.fio_radon(n), x, xi, n, ((0, 0), 1.0), 4, 1e-6, 10 ** 6)
+    F = _import(bf, ["bf16x3", "c64"])
+    _check_both(F, bf, n * n, n * n, 70, "bf16x3")
+    _check_both(F, bf, n * n, n * n, 70, "c64")
