@@ -250,6 +250,39 @@ typedef struct {
 mbf_status mbf_profile_begin(mbf_factor f, int32_t max_launches);
 mbf_status mbf_profile_end(mbf_factor f, mbf_launch_record* out, int32_t cap, int32_t* count);
 
+/* Serving: a request loop over resident factorizations with continuous
+ * batching and memory admission.  mbf_server_create reserves mem_budget
+ * bytes of device memory (the only allocation of the server) and nslots
+ * HIP streams (default priority).  A dispatcher thread forms batches from
+ * queued requests on the same (factor, precision), up to max_batch_rhs
+ * columns; a batch is admitted when a slot is free and the pool can hold
+ * its staging (g and u blocks) and workspace; batches on different slots
+ * run concurrently.  Requests that arrive while others are on the GPU join
+ * the next batches as slots and memory free up.
+ *   submit: u = K g for one request (device pointers owned by the caller,
+ *           unchanged until the request completes); returns its id.
+ *   poll:   *done = 1 once u holds the result; latency = completion -
+ *           submission on the host clock (microseconds).  A request that
+ *           can never fit the budget completes with MBF_ERR_OOM.
+ *   drain:  waits until every submitted request has completed.
+ *   stats:  p50 / p99 / mean latency, requests, RHS, batches, the largest
+ *           number of batches in flight at once, wall time first submit ->
+ *           last completion.
+ * A factor must outlive every request that names it.  Submit, poll, drain
+ * and stats may be called from any host thread. */
+typedef struct mbf_server_s* mbf_server;
+typedef struct {
+  int64_t requests, rhs, batches, max_concurrent_batches;
+  double p50_us, p99_us, mean_us, wall_s;
+} mbf_server_stats_t;
+mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, mbf_server* out);
+mbf_status mbf_server_submit(mbf_server s, mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg,
+                             void* u, int64_t ldu, uint64_t* id);
+mbf_status mbf_server_poll(mbf_server s, uint64_t id, int32_t* done, double* latency_us);
+mbf_status mbf_server_drain(mbf_server s);
+mbf_status mbf_server_stats(mbf_server s, mbf_server_stats_t* out);
+void mbf_server_destroy(mbf_server s);
+
 void mbf_destroy(mbf_factor f);
 const char* mbf_last_error(void);
 

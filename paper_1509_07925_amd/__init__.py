@@ -62,12 +62,20 @@ class LaunchRecord(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("rhs", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_concurrent_batches", ctypes.c_int64), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
 ENTRY_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double))
 
 EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
-           "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end"]
+           "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
+           "mbf_server_submit", "mbf_server_poll", "mbf_server_drain", "mbf_server_stats",
+           "mbf_server_destroy"]
 
 
 def lib():
@@ -90,11 +98,20 @@ def lib():
     L.mbf_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.mbf_profile_begin.argtypes = [vp, i32]
     L.mbf_profile_end.argtypes = [vp, ctypes.POINTER(LaunchRecord), i32, ctypes.POINTER(i32)]
+    L.mbf_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.POINTER(vp)]
+    L.mbf_server_submit.argtypes = [vp, vp, i32, i64, vp, i64, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
+    L.mbf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.mbf_server_drain.argtypes = [vp]
+    L.mbf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.mbf_server_destroy.argtypes = [vp]
+    L.mbf_server_destroy.restype = None
     L.mbf_destroy.argtypes = [vp]
     L.mbf_destroy.restype = None
     L.mbf_last_error.restype = ctypes.c_char_p
     for name in ("mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
-                 "mbf_apply_adjoint", "mbf_info", "mbf_profile_begin", "mbf_profile_end"):
+                 "mbf_apply_adjoint", "mbf_info", "mbf_profile_begin", "mbf_profile_end",
+                 "mbf_server_create", "mbf_server_submit", "mbf_server_poll", "mbf_server_drain",
+                 "mbf_server_stats"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -278,3 +295,55 @@ def multiscale_assemble(parts, part_idx, nxi, center_idx, center, precs=("c64",)
         p._h = None
     _check(st)
     return Factor(h)
+
+
+class Server:
+    """Request loop with continuous batching and memory admission (mbf_server_*)."""
+
+    def __init__(self, mem_budget, nslots=4, max_batch_rhs=256):
+        self._h = ctypes.c_void_p()
+        _check(lib().mbf_server_create(int(mem_budget), nslots, max_batch_rhs, ctypes.byref(self._h)))
+        self._live = {}
+
+    def submit(self, factor, g, out, prec="c64"):
+        """Queue u = K g (g, out: column-major CUDA tensors); returns the request id."""
+        G = g.reshape(-1, 1) if g.dim() == 1 else g
+        O = out.reshape(-1, 1) if out.dim() == 1 else out
+        nrhs = G.shape[1]
+        if G.stride(0) != 1 or O.stride(0) != 1 or O.shape[1] != nrhs:
+            raise ValueError("column-major tensors with matching columns required")
+        ldg = G.stride(1) if nrhs > 1 else G.shape[0]
+        ldo = O.stride(1) if nrhs > 1 else O.shape[0]
+        rid = ctypes.c_uint64()
+        _check(lib().mbf_server_submit(self._h, factor._h, PREC[prec], nrhs, ctypes.c_void_p(G.data_ptr()), ldg,
+                                       ctypes.c_void_p(O.data_ptr()), ldo, ctypes.byref(rid)))
+        self._live[rid.value] = (factor, g, out)
+        return rid.value
+
+    def poll(self, rid):
+        done = ctypes.c_int32()
+        lat = ctypes.c_double()
+        _check(lib().mbf_server_poll(self._h, rid, ctypes.byref(done), ctypes.byref(lat)))
+        if done.value:
+            self._live.pop(rid, None)
+        return bool(done.value), lat.value
+
+    def drain(self):
+        _check(lib().mbf_server_drain(self._h))
+        self._live.clear()
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().mbf_server_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().mbf_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -153,8 +153,19 @@ Low sampled_svd(const Ctx& c, const std::vector<int64_t>& ra, const std::vector<
 // q0 and doubles while the rank found reaches q - oversample; the random
 // stream depends only on (seed, ia, ib, q), so the U and V passes obtain
 // identical factors for the same pair.
+std::atomic<int64_t> g_mid_us{0}, g_rec_us{0};
+struct ScopedUs {
+  std::atomic<int64_t>& acc;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  explicit ScopedUs(std::atomic<int64_t>& a) : acc(a) {}
+  ~ScopedUs() {
+    acc += std::chrono::duration_cast<std::chrono::microseconds>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
 Low middle_pair(const Ctx& c, const Tree& xt, const Tree& ot, int m, int32_t ia, int32_t ib,
                 const mbf_opts& o, int64_t q0, int64_t* rank_out = nullptr) {
+  ScopedUs timer(g_mid_us);
   const int L = xt.L;
   std::vector<int64_t> ra, cb;
   for (int64_t p = xt.off[m][ia]; p < xt.off[m][ia + 1]; ++p) ra.push_back((*c.xs)[xt.perm[p]]);
@@ -326,7 +337,11 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
           for (int32_t it = xt.cfirst[s][ia]; it < xt.cfirst[s][ia + 1]; ++it) {
             const int64_t r0 = xt.off[s + 1][it] - xt.off[s][ia];
             const int64_t r1 = xt.off[s + 1][it + 1] - xt.off[s][ia];
-            la::Trunc t = la::truncated_svd(merge_rows(parts, r0, r1), o.tol, o.max_rank);
+            la::Trunc t;
+            {
+              ScopedUs timer(g_rec_us);
+              t = la::truncated_svd(merge_rows(parts, r0, r1), o.tol, o.max_rank);
+            }
             const int64_t r = (int64_t)t.s.size();
             Mat Uf = t.U0;
             for (int64_t j = 0; j < r; ++j)
@@ -385,7 +400,11 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
           for (int32_t ibc = ot.cfirst[lb][ib]; ibc < ot.cfirst[lb][ib + 1]; ++ibc) {
             const int64_t r0 = ot.off[lb + 1][ibc] - ot.off[lb][ib];
             const int64_t r1 = ot.off[lb + 1][ibc + 1] - ot.off[lb][ib];
-            la::Trunc t = la::truncated_svd(merge_rows(parts, r0, r1), o.tol, o.max_rank);
+            la::Trunc t;
+            {
+              ScopedUs timer(g_rec_us);
+              t = la::truncated_svd(merge_rows(parts, r0, r1), o.tol, o.max_rank);
+            }
             const int64_t r = (int64_t)t.s.size();
             Mat Vf = t.U0;
             for (int64_t j = 0; j < r; ++j)
@@ -417,6 +436,9 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
     pv.tick();
   });
 
+  if (std::getenv("MBF_VERBOSE"))
+    std::fprintf(stderr, "[mbf build] thread-seconds: middle level %.1f, recursion %.1f\n", g_mid_us * 1e-6,
+                 g_rec_us * 1e-6);
   for (size_t p = 0; p < rank_m_v.size(); ++p)
     if (rank_m_v[p] != f.rank[m][p]) throw std::runtime_error("middle-level ranks of the U and V passes differ");
   for (int s = 0; s <= L; ++s)

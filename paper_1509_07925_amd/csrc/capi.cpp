@@ -11,9 +11,6 @@
 #include "device.h"
 #include "factor.h"
 
-struct mbf_factor_s {
-  mbf::DevFactor dev;
-};
 
 namespace mbf {
 namespace {

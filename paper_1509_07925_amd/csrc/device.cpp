@@ -73,6 +73,39 @@ Error upload_split(const cd* src, size_t count, void** dst, size_t& bytes) {
   return dev_alloc_copy(dst, tmp.data(), tmp.size(), bytes);
 }
 
+// Convert `count` complex128 entries to the storage of precision p and copy
+// them to dst (device), in chunks.
+Error copy_blocks(int p, const cd* src, size_t count, void* dst) {
+  const size_t chunk = (size_t)1 << 24;
+  for (size_t o = 0; o < count; o += chunk) {
+    const size_t c = std::min(chunk, count - o);
+    hipError_t e;
+    if (p == MBF_C128) {
+      e = hipMemcpy((char*)dst + o * 16, src + o, c * 16, hipMemcpyHostToDevice);
+    } else if (p == MBF_C64) {
+      std::vector<float> t(2 * c);
+      for (size_t i = 0; i < c; ++i) {
+        t[2 * i] = (float)src[o + i].real();
+        t[2 * i + 1] = (float)src[o + i].imag();
+      }
+      e = hipMemcpy((char*)dst + o * 8, t.data(), c * 8, hipMemcpyHostToDevice);
+    } else {
+      std::vector<bf16x4> t(c);
+      for (size_t i = 0; i < c; ++i) {
+        float re = (float)src[o + i].real(), im = (float)src[o + i].imag();
+        uint16_t rh = f2bf(re), ih = f2bf(im);
+        t[i].v[0] = rh;
+        t[i].v[1] = ih;
+        t[i].v[2] = f2bf(re - bf2f(rh));
+        t[i].v[3] = f2bf(im - bf2f(ih));
+      }
+      e = hipMemcpy((char*)dst + o * 8, t.data(), c * 8, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return {MBF_ERR_HIP, std::string("hipMemcpy failed: ") + hipGetErrorString(e)};
+  }
+  return {MBF_OK, ""};
+}
+
 Error upload_real(int p, const double* src, size_t count, void** dst, size_t& bytes) {
   if (p == MBF_C128) return dev_alloc_copy(dst, src, count, bytes);
   std::vector<float> tmp(count);
@@ -207,36 +240,31 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
   MBF_TRY(dev_alloc_copy((void**)&P.d_vidx, vidx.data(), vidx.size(), meta));
   MBF_TRY(dev_alloc_copy((void**)&P.d_uidx, uidx.data(), uidx.size(), meta));
 
-  // Concatenate host blocks once per upload.
-  std::vector<cd> Wall((size_t)woff), Vall((size_t)P.v_elems), Uall((size_t)P.u_elems);
-  {
-    size_t o = 0;
-    for (int s = 0; s < L; ++s) {
-      std::copy(f.W[s].begin(), f.W[s].end(), Wall.begin() + o);
-      o += f.W[s].size();
-    }
-    o = 0;
-    for (auto& v : f.V0) {
-      std::copy(v.begin(), v.end(), Vall.begin() + o);
-      o += v.size();
-    }
-    o = 0;
-    for (auto& v : f.UL) {
-      std::copy(v.begin(), v.end(), Uall.begin() + o);
-      o += v.size();
-    }
-  }
+  // Upload stage by stage (no host copy of the whole factorization).
   for (int p = 0; p < kNumPrec; ++p) {
     if (!(prec_mask & (1u << p))) continue;
     PrecData& d = P.prec[p];
     d.present = true;
     const int leafp = (p == MBF_C128) ? MBF_C128 : MBF_C64;
-    if (p == MBF_C64_SPLIT_BF16)
-      MBF_TRY(upload_split(Wall.data(), Wall.size(), &d.W, d.bytes));
-    else
-      MBF_TRY(upload_complex(p, Wall.data(), Wall.size(), &d.W, d.bytes));
-    MBF_TRY(upload_complex(leafp, Vall.data(), Vall.size(), &d.V0, d.bytes));
-    MBF_TRY(upload_complex(leafp, Uall.data(), Uall.size(), &d.UL, d.bytes));
+    const size_t esz = (p == MBF_C128) ? 16 : 8;
+    if (woff > 0) {
+      hipError_t e = hipMalloc(&d.W, (size_t)woff * esz);
+      if (e != hipSuccess) {
+        d.W = nullptr;
+        return {e == hipErrorOutOfMemory ? MBF_ERR_OOM : MBF_ERR_HIP,
+                std::string("hipMalloc (stage blocks) failed: ") + hipGetErrorString(e)};
+      }
+      d.bytes += (size_t)woff * esz;
+      for (int s = 0; s < L; ++s)
+        MBF_TRY(copy_blocks(p, f.W[s].data(), f.W[s].size(), (char*)d.W + (size_t)P.w_stage_off[s] * esz));
+    }
+    std::vector<cd> tmp;
+    tmp.reserve((size_t)std::max(P.v_elems, P.u_elems));
+    for (auto& v : f.V0) tmp.insert(tmp.end(), v.begin(), v.end());
+    MBF_TRY(upload_complex(leafp, tmp.data(), tmp.size(), &d.V0, d.bytes));
+    tmp.clear();
+    for (auto& v : f.UL) tmp.insert(tmp.end(), v.begin(), v.end());
+    MBF_TRY(upload_complex(leafp, tmp.data(), tmp.size(), &d.UL, d.bytes));
     MBF_TRY(upload_real(leafp, f.S.data(), f.S.size(), &d.S, d.bytes));
   }
   return {MBF_OK, ""};

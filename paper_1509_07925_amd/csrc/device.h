@@ -104,3 +104,8 @@ Error launch_apply(const DevFactor& F, int prec, bool adjoint, int64_t nrhs, con
                    hipStream_t stream);
 
 }  // namespace mbf
+
+// The opaque handle of the C ABI.
+struct mbf_factor_s {
+  mbf::DevFactor dev;
+};

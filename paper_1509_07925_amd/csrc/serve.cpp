@@ -1,0 +1,370 @@
+// Request loop over resident factorizations: continuous batching with
+// memory admission (see include/mbf.h, "Serving").
+//
+// A dispatcher thread owns `nslots` HIP streams.  Submitted requests wait in
+// a FIFO.  Whenever a slot is free, the dispatcher forms a batch from the
+// oldest request and every queued request on the same (factor, precision),
+// up to max_batch_rhs columns, reserves the batch's staging and workspace
+// bytes from the server's device pool (admission: the batch waits while the
+// pool cannot hold it), and enqueues on the slot's stream:
+//   gather the requests' g columns into one contiguous block,
+//   one mbf_apply over all columns (the factor is read once per batch),
+//   scatter the result columns to each request's u,
+//   an event marking completion.
+// Batches on different slots overlap on the device.  Completion is observed
+// by polling the events; a request's latency is completion - submission on
+// the host clock.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "device.h"
+#include "factor.h"
+
+
+namespace mbf {
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t id;
+  mbf_factor f;
+  int prec;
+  int64_t nrhs;
+  const void* g;
+  int64_t ldg;
+  void* u;
+  int64_t ldu;
+  clk::time_point t_submit;
+};
+
+// First-fit allocator over one device allocation (offsets 256-byte aligned).
+struct Pool {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  bool init(size_t bytes) {
+    size = bytes;
+    if (hipMalloc((void**)&base, bytes) != hipSuccess) {
+      base = nullptr;
+      return false;
+    }
+    free_[0] = bytes;
+    return true;
+  }
+  size_t alloc(size_t bytes) {  // returns SIZE_MAX when full
+    bytes = (bytes + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        return off;
+      }
+    return SIZE_MAX;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<Request> reqs;
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct Server {
+  int device = 0;
+  Pool pool;
+  std::vector<Slot> slots;
+  int64_t max_batch_rhs = 256;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request> queue;
+  std::map<uint64_t, double> done_latency_us;  // completed requests
+  std::vector<double> all_latency_us;
+  std::atomic<uint64_t> next_id{1};
+  bool stop = false;
+  std::string error;
+  int64_t batches = 0, rhs_done = 0, requests_done = 0, max_concurrent = 0;
+  clk::time_point t_first{}, t_last{};
+  std::thread th;
+
+  size_t batch_bytes(const Request& r, int64_t nrhs) const {
+    const DevFactor& F = r.f->dev;
+    const size_t es = r.prec == MBF_C128 ? 16 : 8;
+    const size_t io = (size_t)(F.nxi + F.nx) * (size_t)nrhs * es;
+    return (io + 255) / 256 * 256 + workspace_bytes(F, r.prec, nrhs);
+  }
+
+  // Launch one batch on slot s; called with mu held.
+  bool launch(Slot& s) {
+    if (queue.empty()) return false;
+    const Request head = queue.front();
+    std::vector<size_t> take;
+    int64_t cols = 0;
+    for (size_t i = 0; i < queue.size(); ++i) {
+      const Request& r = queue[i];
+      if (r.f != head.f || r.prec != head.prec) continue;
+      if (cols > 0 && cols + r.nrhs > max_batch_rhs) break;
+      take.push_back(i);
+      cols += r.nrhs;
+    }
+    const size_t need = batch_bytes(head, cols);
+    if (need > pool.size) {
+      error = "request larger than the server memory budget";
+      // fail the head request immediately
+      done_latency_us[head.id] = -1.0;
+      queue.pop_front();
+      return true;
+    }
+    const size_t off = pool.alloc(need);
+    if (off == SIZE_MAX) return false;  // admission: wait for memory
+    const DevFactor& F = head.f->dev;
+    const size_t es = head.prec == MBF_C128 ? 16 : 8;
+    char* gb = pool.base + off;
+    char* ub = gb + (size_t)F.nxi * cols * es;
+    const size_t io = (size_t)(F.nxi + F.nx) * (size_t)cols * es;
+    char* ws = pool.base + off + (io + 255) / 256 * 256;
+    s.reqs.clear();
+    int64_t c0 = 0;
+    for (size_t k = 0; k < take.size(); ++k) {
+      const Request& r = queue[take[k]];
+      (void)hipMemcpy2DAsync(gb + (size_t)c0 * F.nxi * es, (size_t)F.nxi * es, r.g, (size_t)r.ldg * es,
+                             (size_t)F.nxi * es, (size_t)r.nrhs, hipMemcpyDeviceToDevice, s.stream);
+      c0 += r.nrhs;
+      s.reqs.push_back(r);
+    }
+    Error e = launch_apply(F, head.prec, false, cols, gb, F.nxi, ub, F.nx, ws, need - (ws - gb), s.stream);
+    if (e.st != MBF_OK) error = e.msg;
+    c0 = 0;
+    for (const Request& r : s.reqs) {
+      (void)hipMemcpy2DAsync(r.u, (size_t)r.ldu * es, ub + (size_t)c0 * F.nx * es, (size_t)F.nx * es,
+                             (size_t)F.nx * es, (size_t)r.nrhs, hipMemcpyDeviceToDevice, s.stream);
+      c0 += r.nrhs;
+    }
+    (void)hipEventRecord(s.done, s.stream);
+    for (size_t k = take.size(); k-- > 0;) queue.erase(queue.begin() + (std::ptrdiff_t)take[k]);
+    s.busy = true;
+    s.off = off;
+    s.bytes = need;
+    ++batches;
+    return true;
+  }
+
+  void loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      // completions
+      int64_t active = 0;
+      for (auto& s : slots) {
+        if (!s.busy) continue;
+        if (hipEventQuery(s.done) == hipSuccess) {
+          const auto now = clk::now();
+          for (const Request& r : s.reqs) {
+            const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
+            done_latency_us[r.id] = us;
+            all_latency_us.push_back(us);
+            rhs_done += r.nrhs;
+            ++requests_done;
+          }
+          t_last = now;
+          pool.release(s.off, s.bytes);
+          s.busy = false;
+          s.reqs.clear();
+        } else {
+          ++active;
+        }
+      }
+      // admissions
+      bool progressed = true;
+      while (progressed && !queue.empty()) {
+        progressed = false;
+        for (auto& s : slots)
+          if (!s.busy && launch(s)) {
+            progressed = true;
+            if (s.busy) ++active;
+            break;
+          }
+      }
+      max_concurrent = std::max(max_concurrent, active);
+      if (stop && queue.empty() && active == 0) break;
+      cv.notify_all();
+      cv.wait_for(lk, std::chrono::microseconds(active ? 20 : 500));
+    }
+    cv.notify_all();
+  }
+};
+
+}  // namespace mbf
+
+using mbf::Server;
+struct mbf_server_s : Server {};
+
+extern "C" {
+
+mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, mbf_server* out) {
+  if (!out || mem_budget == 0 || nslots <= 0 || nslots > 64 || max_batch_rhs <= 0) {
+    mbf::set_error("invalid server arguments");
+    return MBF_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  mbf_server_s* s = new mbf_server_s();
+  (void)hipGetDevice(&s->device);
+  if (!s->pool.init(mem_budget)) {
+    delete s;
+    mbf::set_error("server memory budget allocation failed");
+    return MBF_ERR_OOM;
+  }
+  s->max_batch_rhs = max_batch_rhs;
+  s->slots.resize(nslots);
+  for (auto& sl : s->slots) {
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      mbf::set_error("stream/event creation failed");
+      for (auto& q : s->slots) {
+        if (q.stream) (void)hipStreamDestroy(q.stream);
+        if (q.done) (void)hipEventDestroy(q.done);
+      }
+      (void)hipFree(s->pool.base);
+      delete s;
+      return MBF_ERR_HIP;
+    }
+  }
+  s->th = std::thread([s]() { s->loop(); });
+  *out = s;
+  return MBF_OK;
+}
+
+mbf_status mbf_server_submit(mbf_server srv, mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg,
+                             void* u, int64_t ldu, uint64_t* id) {
+  Server* s = srv;
+  if (!s || !f || !g || !u || !id || nrhs <= 0 || p < 0 || p >= mbf::kNumPrec) {
+    mbf::set_error("invalid submit arguments");
+    return MBF_ERR_INVALID_ARG;
+  }
+  if (!(f->dev.prec_mask & (1u << p))) {
+    mbf::set_error("precision not built for this factor");
+    return MBF_ERR_UNSUPPORTED;
+  }
+  if (ldg < f->dev.nxi || ldu < f->dev.nx) {
+    mbf::set_error("leading dimension too small");
+    return MBF_ERR_INVALID_ARG;
+  }
+  mbf::Request r{s->next_id++, f, (int)p, nrhs, g, ldg, u, ldu, mbf::clk::now()};
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      mbf::set_error("server is shutting down");
+      return MBF_ERR_BUSY;
+    }
+    if (s->requests_done == 0 && s->queue.empty()) s->t_first = r.t_submit;
+    s->queue.push_back(r);
+  }
+  s->cv.notify_all();
+  *id = r.id;
+  return MBF_OK;
+}
+
+mbf_status mbf_server_poll(mbf_server srv, uint64_t id, int32_t* done, double* latency_us) {
+  Server* s = srv;
+  if (!s || !done) {
+    mbf::set_error("invalid poll arguments");
+    return MBF_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->done_latency_us.find(id);
+  *done = it != s->done_latency_us.end();
+  if (*done && it->second < 0) {
+    mbf::set_error(s->error);
+    return MBF_ERR_OOM;
+  }
+  if (latency_us) *latency_us = *done ? it->second : 0.0;
+  return MBF_OK;
+}
+
+mbf_status mbf_server_drain(mbf_server srv) {
+  Server* s = srv;
+  if (!s) return MBF_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv.wait(lk, [&]() {
+    if (!s->queue.empty()) return false;
+    for (auto& sl : s->slots)
+      if (sl.busy) return false;
+    return true;
+  });
+  if (!s->error.empty()) {
+    mbf::set_error(s->error);
+    return MBF_ERR_HIP;
+  }
+  return MBF_OK;
+}
+
+mbf_status mbf_server_stats(mbf_server srv, mbf_server_stats_t* out) {
+  Server* s = srv;
+  if (!s || !out) return MBF_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  std::vector<double> v = s->all_latency_us;
+  std::sort(v.begin(), v.end());
+  auto pct = [&](double q) { return v.empty() ? 0.0 : v[std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5))]; };
+  out->requests = s->requests_done;
+  out->rhs = s->rhs_done;
+  out->batches = s->batches;
+  out->max_concurrent_batches = s->max_concurrent;
+  out->p50_us = pct(0.50);
+  out->p99_us = pct(0.99);
+  out->mean_us = v.empty() ? 0.0 : [&]() { double t = 0; for (double x : v) t += x; return t / v.size(); }();
+  out->wall_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
+  return MBF_OK;
+}
+
+void mbf_server_destroy(mbf_server srv) {
+  mbf_server_s* s = srv;
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (auto& sl : s->slots) {
+    (void)hipStreamSynchronize(sl.stream);
+    (void)hipStreamDestroy(sl.stream);
+    (void)hipEventDestroy(sl.done);
+  }
+  (void)hipFree(s->pool.base);
+  delete s;
+}
+
+}  // extern "C"
