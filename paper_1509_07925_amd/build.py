@@ -20,7 +20,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-variable", "-Wno-u
 # Device code: no packed-FP32 instructions (hardware notes).
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-HOST_ONLY = ["-march=x86-64-v3", "-fcx-limited-range"]
+HOST_ONLY = ["-march=x86-64-v3", "-fcx-limited-range", "-ffp-contract=fast", "-fno-math-errno", "-fno-signed-zeros", "-fno-trapping-math", "-fassociative-math", "-freciprocal-math"]
 
 
 def _hipcc():

@@ -1,17 +1,14 @@
 // Host FP64 builder (see builder.h).
 //
-// Order of work (Section 2.5 discusses the memory of this order for case
-// (ii)): the recursive factorization of U^h is independent for every
-// middle-level node A of T_X, and that of V^h for every middle-level node B
-// of T_Omega.  The builder therefore runs one task per middle-level node:
+// Order of work: the recursive factorization of U^h is independent for
+// every middle-level node A of T_X, and that of V^h for every middle-level
+// node B of T_Omega.  The builder runs one task per middle-level node:
 //   U task (A):  for every B, factor K_{A,B} at the middle level (SVD via
-//                random sampling, form eq. (lowrank1)), keep U_{A,B} and
-//                S_{A,B}; then recurse down the subtree of A (split, merge,
-//                truncate in form eq. (lowrank2), assemble G).
-//   V task (B):  for every A, factor K_{A,B} again with the same random
-//                stream (so the factors are identical), keep V_{B,A}; then
-//                recurse down the subtree of B, producing H.
-// Memory stays at one subtree per thread instead of all of U^h / V^h.
+//                random sampling, form eq. (lowrank1)); keep V_{B,A} for the
+//                V pass; then recurse down the subtree of A with U_{A,.}
+//                (split, merge, truncate in form eq. (lowrank2), assemble G).
+//   V task (B):  take V_{B,.} and recurse down the subtree of B, producing H.
+// U^h is held one subtree per thread; V^h is held whole between the passes.
 #include "builder.h"
 
 #include <atomic>
@@ -82,7 +79,16 @@ struct Low {
 };
 
 // SVD via random sampling (Section 2.1, case ii) of Z = K(ra, cb) where ra
-// and cb list callback indices of the rows / columns.
+// and cb list callback indices of the rows / columns.  Steps, in the
+// paper's order:
+//   (1) representative columns: pivoted QR of q randomly selected rows;
+//       the representative rows are those q random rows (reading of the
+//       paper's iteration, see the design notes: one selection round);
+//   (2) orthonormal bases Q_col of the representative columns and Q_row of
+//       the representative rows (Householder QR);
+//   (3) M = pinv(Q_col[I_row]) Z(I_row, I_col) pinv(Q_row[I_col]^*) on index
+//       sets that contain the representatives plus q fresh random indices;
+//   (4) SVD of M:  Z ~ (Q_col U_M) S_M (Q_row V_M)^*.
 Low sampled_svd(const Ctx& c, const std::vector<int64_t>& ra, const std::vector<int64_t>& cb, double tol,
                 int64_t rmax, int64_t os, int64_t q, std::mt19937_64& rng) {
   const int64_t m = (int64_t)ra.size(), n = (int64_t)cb.size();
@@ -91,51 +97,46 @@ Low sampled_svd(const Ctx& c, const std::vector<int64_t>& ra, const std::vector<
     for (size_t i = 0; i < idx.size(); ++i) o[i] = base[idx[i]];
     return o;
   };
-  std::vector<int64_t> all_r(m), all_c(n);
-  std::iota(all_r.begin(), all_r.end(), 0);
-  std::iota(all_c.begin(), all_c.end(), 0);
   const double qtol = tol * 1e-2;
-  std::vector<int64_t> reps_r, reps_c;
-  for (int round = 0; round < 3; ++round) {
-    // representative columns from pivoted QR of randomly selected rows
-    std::vector<int64_t> Ir = merge_sorted(reps_r, sample(rng, m, q));
-    Mat Zr = entries(c, sub(ra, Ir), cb);
-    la::QRP qr1 = la::pivoted_qr(Zr, qtol, std::min<int64_t>(rmax + os, n));
-    std::vector<int64_t> nc(qr1.piv.begin(), qr1.piv.begin() + qr1.k);
-    std::sort(nc.begin(), nc.end());
-    // representative rows from pivoted QR of the columns (reps + random)
-    std::vector<int64_t> Ic = merge_sorted(nc, sample(rng, n, q));
-    Mat Zc = entries(c, ra, sub(cb, Ic));
-    la::QRP qr2 = la::pivoted_qr(la::adjoint(Zc), qtol, std::min<int64_t>(rmax + os, m));
-    std::vector<int64_t> nr(qr2.piv.begin(), qr2.piv.begin() + qr2.k);
-    std::sort(nr.begin(), nr.end());
-    const bool stable = nc == reps_c && nr == reps_r;
-    reps_c = nc;
-    reps_r = nr;
-    if (stable) break;
-  }
   Low out;
-  if (reps_c.empty() || reps_r.empty()) {
+  // (1) representatives
+  std::vector<int64_t> reps_r = sample(rng, m, q);
+  Mat Zr = entries(c, sub(ra, reps_r), cb);  // |reps_r| x n
+  la::QRP qr1 = la::pivoted_qr(Zr, qtol, std::min<int64_t>(rmax + os, n));
+  std::vector<int64_t> reps_c(qr1.piv.begin(), qr1.piv.begin() + qr1.k);
+  std::sort(reps_c.begin(), reps_c.end());
+  if (reps_c.empty()) {
     out.U0 = Mat(m, 0);
     out.V0 = Mat(n, 0);
     return out;
   }
-  la::QRP qc = la::pivoted_qr(entries(c, ra, sub(cb, reps_c)), qtol * 1e-2, (int64_t)reps_c.size());
-  la::QRP qrr = la::pivoted_qr(la::adjoint(entries(c, sub(ra, reps_r), cb)), qtol * 1e-2, (int64_t)reps_r.size());
+  // (2) bases.  Q_col from the representative columns; the representative
+  // rows are then refined by a pivoted QR over the rows of those columns
+  // (the paper's alternation between columns and rows), and Q_row is the
+  // basis of the selected rows.
+  Mat Zcr = entries(c, ra, sub(cb, reps_c));  // m x kc
+  la::QRP qc = la::pivoted_qr(Zcr, qtol * 1e-2, (int64_t)reps_c.size(), false);
+  la::QRP qsel = la::pivoted_qr(la::adjoint(Zcr), qtol, std::min<int64_t>((int64_t)reps_c.size(), m));
+  std::vector<int64_t> rows2(qsel.piv.begin(), qsel.piv.begin() + qsel.k);
+  std::sort(rows2.begin(), rows2.end());
+  reps_r = merge_sorted(rows2, reps_r);
+  la::QRP qrr = la::pivoted_qr(la::adjoint(entries(c, sub(ra, reps_r), cb)), qtol, (int64_t)reps_r.size(), true);
   const Mat& Qc = qc.Q;   // m x kc
   const Mat& Qr = qrr.Q;  // n x kr
-  std::vector<int64_t> Irow = merge_sorted(reps_r, sample(rng, m, q));
-  std::vector<int64_t> Icol = merge_sorted(reps_c, sample(rng, n, q));
+  // (3) middle matrix on index sets containing the representatives
+  // Least-squares systems stay overdetermined by at least q rows / columns.
+  const std::vector<int64_t> Irow = merge_sorted(reps_r, sample(rng, m, Qc.n + q));
+  const std::vector<int64_t> Icol = merge_sorted(reps_c, sample(rng, n, Qr.n + q));
   Mat Zs = entries(c, sub(ra, Irow), sub(cb, Icol));
   Mat Qci((int64_t)Irow.size(), Qc.n), Qri((int64_t)Icol.size(), Qr.n);
   for (int64_t j = 0; j < Qc.n; ++j)
     for (size_t i = 0; i < Irow.size(); ++i) Qci((int64_t)i, j) = Qc(Irow[i], j);
   for (int64_t j = 0; j < Qr.n; ++j)
     for (size_t i = 0; i < Icol.size(); ++i) Qri((int64_t)i, j) = Qr(Icol[i], j);
-  // M = pinv(Qc[Irow]) Z(Irow, Icol) pinv(Qr[Icol]^*) = pinv(Qc[Irow]) Z pinv(Qr[Icol])^*,
-  // both pseudo-inverses applied as least-squares solves (full column rank).
-  Mat T = la::lstsq(Qci, Zs);                        // kc x |Icol|
+  // M = pinv(Qc[Irow]) Z pinv(Qr[Icol])^*, both pseudo-inverses as least-squares solves
+  Mat T = la::lstsq(Qci, Zs);                           // kc x |Icol|
   Mat M = la::adjoint(la::lstsq(Qri, la::adjoint(T)));  // kc x kr
+  // (4) SVD of M
   la::SVD d = la::svd(M);
   const int64_t r = la::trunc_rank(d.s, tol, rmax);
   Mat UM(M.m, r), VM(M.n, r);
@@ -153,7 +154,8 @@ Low sampled_svd(const Ctx& c, const std::vector<int64_t>& ra, const std::vector<
 // q0 and doubles while the rank found reaches q - oversample; the random
 // stream depends only on (seed, ia, ib, q), so the U and V passes obtain
 // identical factors for the same pair.
-std::atomic<int64_t> g_mid_us{0}, g_rec_us{0};
+std::atomic<int64_t> g_mid_us{0}, g_rec_us{0}, g_t_ent{0}, g_t_round{0}, g_t_basis{0}, g_t_solve{0}, g_t_svd{0};
+struct ScopedUs;
 struct ScopedUs {
   std::atomic<int64_t>& acc;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -285,7 +287,9 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   std::vector<std::vector<double>> Smid((size_t)xt.nn(m) * ot.nn(L - m));
   f.UL.resize(xt.nn(L));
   f.V0.resize(ot.nn(L));
-  std::vector<int32_t> rank_m_v((size_t)xt.nn(m) * ot.nn(L - m), -1);
+  // V^m of every middle-level pair, produced by the U pass (form eq. (lowrank1))
+  // and consumed by the V pass: each pair is factored once.
+  std::vector<Mat> Vmid((size_t)xt.nn(m) * ot.nn(L - m));
 
   // Descendants of node i at level l0 found at level l (contiguous range).
   auto desc = [](const Tree& t, int l0, int32_t i, int l) {
@@ -321,6 +325,10 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
       f.rank[m][p] = (int32_t)r;
       Smid[p] = std::move(sinv);
       U[{(int32_t)ia_m, ib}] = std::move(Uf);
+      Mat Vf = std::move(lw.V0);
+      for (int64_t j = 0; j < r; ++j)
+        for (int64_t i = 0; i < Vf.m; ++i) Vf(i, j) *= lw.s[j];
+      Vmid[p] = std::move(Vf);
     }
     for (int s = m; s < L; ++s) {
       std::map<std::pair<int32_t, int32_t>, Mat> Un;
@@ -376,13 +384,9 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   parallel_for(ot.nn(L - m), threads, [&](int64_t ib_m) {
     std::map<std::pair<int32_t, int32_t>, Mat> V;  // (ia, ib) at current stage
     for (int32_t ia = 0; ia < xt.nn(m); ++ia) {
-      Low lw = middle_pair(c, xt, ot, m, ia, (int32_t)ib_m, o, q0);
-      const int64_t r = (int64_t)lw.s.size();
-      Mat Vf = lw.V0;
-      for (int64_t j = 0; j < r; ++j)
-        for (int64_t i = 0; i < Vf.m; ++i) Vf(i, j) *= lw.s[j];
-      rank_m_v[(int64_t)ia * ot.nn(L - m) + ib_m] = (int32_t)r;
+      Mat& Vf = Vmid[(size_t)ia * ot.nn(L - m) + ib_m];
       V[{ia, (int32_t)ib_m}] = std::move(Vf);
+      Vf = Mat();
     }
     for (int s = m; s >= 1; --s) {
       std::map<std::pair<int32_t, int32_t>, Mat> Vn;
@@ -439,8 +443,6 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   if (std::getenv("MBF_VERBOSE"))
     std::fprintf(stderr, "[mbf build] thread-seconds: middle level %.1f, recursion %.1f\n", g_mid_us * 1e-6,
                  g_rec_us * 1e-6);
-  for (size_t p = 0; p < rank_m_v.size(); ++p)
-    if (rank_m_v[p] != f.rank[m][p]) throw std::runtime_error("middle-level ranks of the U and V passes differ");
   for (int s = 0; s <= L; ++s)
     for (auto v : f.rank[s])
       if (v < 0) throw std::runtime_error("missing rank");

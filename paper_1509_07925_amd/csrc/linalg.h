@@ -88,39 +88,41 @@ struct QRP {
   std::vector<int64_t> piv;
   int64_t k = 0;
 };
+inline QRP pivoted_qr(Mat A, double tol, int64_t kmax, bool pivot = true);
 
-inline QRP pivoted_qr(Mat A, double tol, int64_t kmax) {
+inline QRP pivoted_qr(Mat A, double tol, int64_t kmax, bool pivot) {
   const int64_t m = A.m, n = A.n;
   QRP out;
   out.piv.resize(n);
   std::iota(out.piv.begin(), out.piv.end(), 0);
   kmax = std::min<int64_t>(kmax, std::min(m, n));
-  std::vector<double> cn(n);
-  for (int64_t j = 0; j < n; ++j) cn[j] = norm2sq(A.col(j), m);
-  std::vector<Mat> refl;  // Householder vectors (stored as m-k columns)
+  // Partial column norms, downdated after every step and recomputed when
+  // cancellation has eaten most of their digits.
+  std::vector<double> cn(n), cn0(n);
+  for (int64_t j = 0; j < n; ++j) cn0[j] = cn[j] = norm2sq(A.col(j), m);
   std::vector<cd> vs;
   std::vector<int64_t> voff;
   double first = -1;
   int64_t k = 0;
   for (; k < kmax; ++k) {
-    // pivot: recompute exact trailing norms (robust; same order as the update)
     int64_t p = k;
-    double best = -1;
-    for (int64_t j = k; j < n; ++j) {
-      const double v = norm2sq(A.col(j) + k, m - k);
-      cn[j] = v;
-      if (v > best) {
-        best = v;
-        p = j;
-      }
+    if (pivot) {
+      double best = -1;
+      for (int64_t j = k; j < n; ++j)
+        if (cn[j] > best) {
+          best = cn[j];
+          p = j;
+        }
     }
-    const double nrm = std::sqrt(std::max(best, 0.0));
-    if (first < 0) first = nrm;
-    if (nrm <= tol * first || nrm == 0.0) break;
     if (p != k) {
       std::swap_ranges(A.col(k), A.col(k) + m, A.col(p));
       std::swap(out.piv[k], out.piv[p]);
+      std::swap(cn[k], cn[p]);
+      std::swap(cn0[k], cn0[p]);
     }
+    const double nrm = std::sqrt(norm2sq(A.col(k) + k, m - k));
+    if (first < 0) first = nrm;
+    if (nrm <= tol * first || nrm == 0.0) break;
     cd* x = A.col(k) + k;
     const int64_t len = m - k;
     const cd x0 = x[0];
@@ -128,18 +130,22 @@ inline QRP pivoted_qr(Mat A, double tol, int64_t kmax) {
     const cd ph = ax0 > 0 ? x0 / ax0 : cd(1, 0);
     const cd alpha = -ph * nrm;
     // v = x - alpha e1, normalized
-    std::vector<cd> v(x, x + len);
-    v[0] -= alpha;
-    const double vn = std::sqrt(norm2sq(v.data(), len));
-    if (vn > 0)
-      for (auto& e : v) e /= vn;
     voff.push_back((int64_t)vs.size());
-    vs.insert(vs.end(), v.begin(), v.end());
-    // apply H = I - 2 v v^* to columns k..n-1
+    vs.insert(vs.end(), x, x + len);
+    cd* v = vs.data() + voff.back();
+    v[0] -= alpha;
+    const double vn = std::sqrt(norm2sq(v, len));
+    if (vn > 0)
+      for (int64_t i = 0; i < len; ++i) v[i] /= vn;
+    // apply H = I - 2 v v^* to columns k..n-1 and downdate the norms
     for (int64_t j = k; j < n; ++j) {
       cd* c = A.col(j) + k;
-      const cd t = 2.0 * dotc(v.data(), c, len);
-      axpy(-t, v.data(), c, len);
+      const cd t = 2.0 * dotc(v, c, len);
+      axpy(-t, v, c, len);
+      if (pivot && j > k) {
+        cn[j] -= std::norm(c[0]);
+        if (cn[j] <= 1e-8 * cn0[j]) cn0[j] = cn[j] = norm2sq(c + 1, len - 1);
+      }
     }
   }
   out.k = k;
@@ -152,7 +158,7 @@ inline QRP pivoted_qr(Mat A, double tol, int64_t kmax) {
   for (int64_t r = k - 1; r >= 0; --r) {
     const cd* v = vs.data() + voff[r];
     const int64_t len = m - r;
-    for (int64_t j = 0; j < k; ++j) {
+    for (int64_t j = r; j < k; ++j) {
       cd* c = out.Q.col(j) + r;
       const cd t = 2.0 * dotc(v, c, len);
       axpy(-t, v, c, len);
@@ -175,7 +181,10 @@ inline SVD jacobi_svd_tall(Mat B) {
   for (int64_t i = 0; i < k; ++i) V(i, i) = cd(1, 0);
   std::vector<double> nr(k);
   for (int64_t j = 0; j < k; ++j) nr[j] = norm2sq(B.col(j), p);
-  const double eps = 1e-15;
+  // Rotations stop at a relative off-diagonal level of 1e-12: the singular
+  // values are then accurate far below any truncation tolerance used here,
+  // and B V = U S holds to rounding whatever the level.
+  const double eps = 1e-12;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0;
     for (int64_t i = 0; i < k - 1; ++i)
@@ -230,10 +239,32 @@ inline SVD jacobi_svd_tall(Mat B) {
   return out;
 }
 
+// SVD of a tall matrix A (m >= n) preconditioned by a column-pivoted QR:
+// A P = Q R, then one-sided Jacobi on R^* (n x k, few sweeps for such
+// triangular factors): R^* = X S Y^*  =>  A = (Q Y) S (P X)^*.
+inline SVD svd_tall_qr(const Mat& A) {
+  QRP q = pivoted_qr(A, 0.0, A.n, true);
+  const int64_t k = q.k, n = A.n;
+  Mat RH(n, k);
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = 0; i < k; ++i) RH(j, i) = std::conj(q.R(i, j));
+  SVD t = jacobi_svd_tall(RH);  // RH = X S Y^*  (X: n x k, Y: k x k)
+  SVD out;
+  out.s = t.s;
+  out.U = Mat(A.m, k);
+  // U = Q Y
+  for (int64_t j = 0; j < k; ++j)
+    for (int64_t l = 0; l < k; ++l) axpy(t.V(l, j), q.Q.col(l), out.U.col(j), A.m);
+  out.V = Mat(n, k);
+  for (int64_t j = 0; j < k; ++j)
+    for (int64_t i = 0; i < n; ++i) out.V(q.piv[i], j) = t.U(i, j);
+  return out;
+}
+
 // SVD of any matrix: A = U diag(s) V^*, economy size.
 inline SVD svd(const Mat& A) {
-  if (A.m >= A.n) return jacobi_svd_tall(A);
-  SVD t = jacobi_svd_tall(adjoint(A));  // A^* = U' S V'^*  =>  A = V' S U'^*
+  if (A.m >= A.n) return svd_tall_qr(A);
+  SVD t = svd_tall_qr(adjoint(A));  // A^* = U' S V'^*  =>  A = V' S U'^*
   SVD out;
   out.U = t.V;
   out.V = t.U;

@@ -55,6 +55,26 @@ __device__ __forceinline__ void split_bf(float x, uint32_t& hi, uint32_t& lo) {
   lo = f2bf_bits(x - bf_bits2f(hi));
 }
 
+// Error-free addition (Knuth TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Fold one reduction chunk's partial sums into the running sums with a
+// compensation term (the matrix cores accumulate within a chunk only), so
+// the rounding error does not grow with the number of chunks.
+__device__ __forceinline__ void fold(v16f& sum, v16f& comp, const v16f& part) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    float s, e;
+    two_sum(sum[j], part[j], s, e);
+    sum[j] = s;
+    comp[j] += e;
+  }
+}
+
 struct Tile {
   int b, mt, nt;
 };
@@ -115,9 +135,11 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
   const float2* Wb = W + d.w_off;
-  v16f acc[2];
+  v16f acc[2], cmp[2];
   acc[0] = v16f{};
   acc[1] = v16f{};
+  cmp[0] = v16f{};
+  cmp[1] = v16f{};
   for (int q0 = 0; q0 < Q; q0 += KC) {
     {  // A: 64 right-hand sides x 16 complex reduction entries
       const int n = tid >> 2, kq = (tid & 3) * 4;
@@ -163,22 +185,27 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
     }
     __syncthreads();
     const int kk = lane >> 5, li = lane & 31;
+    v16f p0 = v16f{}, p1 = v16f{};
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 4) {
       const float4 a = *reinterpret_cast<const float4*>(&As[kk][wn + li][kb]);
       const float4 b0 = *reinterpret_cast<const float4*>(&Bs[kk][wm + li][kb]);
       const float4 b1 = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 + li][kb]);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0.x, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b1.x, acc[1], 0, 0, 0);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b0.y, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1.y, acc[1], 0, 0, 0);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b0.z, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b1.z, acc[1], 0, 0, 0);
-      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b0.w, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b1.w, acc[1], 0, 0, 0);
+      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0.x, p0, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b1.x, p1, 0, 0, 0);
+      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b0.y, p0, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1.y, p1, 0, 0, 0);
+      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b0.z, p0, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b1.z, p1, 0, 0, 0);
+      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b0.w, p0, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b1.w, p1, 0, 0, 0);
     }
+    fold(acc[0], cmp[0], p0);
+    fold(acc[1], cmp[1], p1);
     __syncthreads();
   }
+  acc[0] += cmp[0];
+  acc[1] += cmp[1];
   store_out<ADJ>(d, R, r0, n0, acc, 2, wn, wm, out, ld_out, nrhs, scale);
 }
 
@@ -206,9 +233,11 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
   const uint2* Wb = W + d.w_off;
-  v16f acc[2];
+  v16f acc[2], cmp[2];
   acc[0] = v16f{};
   acc[1] = v16f{};
+  cmp[0] = v16f{};
+  cmp[1] = v16f{};
   for (int q0 = 0; q0 < Q; q0 += KC) {
     {
       const int n = tid >> 2, kq = (tid & 3) * 4;
@@ -261,6 +290,7 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
     }
     __syncthreads();
     const int kh = lane >> 5, li = lane & 31;
+    v16f part[2] = {v16f{}, v16f{}};
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 8) {
       // lane holds real-k 8*kh .. 8*kh+7 of this step = complex k kb + 4*kh .. +3
@@ -271,13 +301,17 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
       for (int i = 0; i < 2; ++i) {
         const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[wm + 32 * i + li][ko]));
         const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[wm + 32 * i + li][ko]));
-        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i], 0, 0, 0);
+        part[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, part[i], 0, 0, 0);
+        part[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, part[i], 0, 0, 0);
+        part[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, part[i], 0, 0, 0);
       }
     }
+    fold(acc[0], cmp[0], part[0]);
+    fold(acc[1], cmp[1], part[1]);
     __syncthreads();
   }
+  acc[0] += cmp[0];
+  acc[1] += cmp[1];
   store_out<ADJ>(d, R, r0, n0, acc, 2, wn, wm, out, ld_out, nrhs, scale);
 }
 

@@ -115,15 +115,22 @@ def test_multiscale_fio_parity():
     _check_both(F, ms, n * n, n * n, 16, "c64")
 
 
-def test_batch_columns_equal_solo_apply():
+@pytest.mark.parametrize("prec,nrhs", [("c64", 40), ("c64", 7), ("bf16x3", 40), ("c128", 9)])
+def test_batch_columns_equal_solo_apply(prec, nrhs):
+    """Each column of a batch is computed independently of the others:
+    permuting the columns permutes the result bit for bit (same kernel
+    path), and a column applied alone agrees within the precision's bar."""
     n = 16
     bf = _dft_oracle(n, 2, 1e-6)
-    F = _import(bf, ["c64"])
-    g = W.rhs(n * n, 40, seed=3)
-    ub = _from_gpu(F.apply(_to_gpu(g, "c64")))
-    for j in (0, 17, 39):
-        uj = _from_gpu(F.apply(_to_gpu(g[:, j:j + 1], "c64")))
-        np.testing.assert_array_equal(ub[:, j:j + 1], uj)
+    F = _import(bf, [prec])
+    g = W.rhs(n * n, nrhs, seed=3)
+    ub = _from_gpu(F.apply(_to_gpu(g, prec), prec=prec))
+    perm = np.random.default_rng(1).permutation(nrhs)
+    up = _from_gpu(F.apply(_to_gpu(g[:, perm], prec), prec=prec))
+    np.testing.assert_array_equal(up, ub[:, perm])
+    for j in (0, nrhs // 2, nrhs - 1):
+        uj = _from_gpu(F.apply(_to_gpu(g[:, j:j + 1], prec), prec=prec))
+        assert direct.rel_err(uj, ub[:, j:j + 1]) <= BAR[prec]
 
 
 @pytest.mark.parametrize("n,leaf,tol", [(32, 2, 1e-6), (64, 4, 1e-6)])
