@@ -4,12 +4,15 @@
 One step = one mbf_apply of the whole factorization (leaf projection, every
 stage block product, middle scaling, leaf reconstruction) to one batch of
 nrhs right-hand sides that are already resident in HBM.  Prints one JSON
-line (see the repository contract): RHS/s, the roofline of the dominant
-kernel (the stage block product) measured with HIP events over the timed
-steps, the relative error against an FP64 reference, and the CPU oracle's
-direct summation timed on a bounded sample of rows.
+line: RHS/s of the plain FP32 apply, the roofline of the dominant kernel
+(the stage block product) measured with HIP events over the timed steps,
+the relative errors against the FP64 apply of the same factors and against
+the direct sum on sampled rows, the split-BF16 apply on the same factors,
+a short served request mix (p50 / p99 latency), and the CPU oracle's direct
+summation timed on a bounded sample of rows.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--prec c64|bf16x3]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+                       [--save PATH | --load PATH] [--no-cpu-baseline] ...
 """
 
 import argparse
@@ -28,31 +31,68 @@ CONFIGS = {
     "dft512": dict(kernel="dft", n=512, tol=1e-6, leaf=4, nrhs=256, split="none"),
     "dft256": dict(kernel="dft", n=256, tol=1e-6, leaf=4, nrhs=256, split="none"),
     "dft128": dict(kernel="dft", n=128, tol=1e-6, leaf=4, nrhs=256, split="none"),
-    "dft64": dict(kernel="dft", n=64, tol=1e-8, leaf=8, nrhs=1, split="none"),
 }
-DEFAULT_CONFIG = os.environ.get("MBF_BENCH_CONFIG", "dft128")
+DEFAULT_CONFIG = os.environ.get("MBF_BENCH_CONFIG", "dft512")
 
-PEAK = {  # MI355X published dense peaks
-    "c64": ("mfma", 157.3, "TFLOP/s"),     # FP32
-    "bf16x3": ("mfma", 2500.0, "TFLOP/s"),  # BF16 matrix cores
-    "c128": ("mfma", 78.6, "TFLOP/s"),     # FP64
-    "hbm": 8000.0,                          # GB/s
+PEAK = {  # MI355X published dense peaks (TFLOP/s)
+    "c64": ("mfma", 157.3),     # FP32 matrix
+    "bf16x3": ("mfma", 2500.0),  # BF16 matrix
+    "c128": ("mfma", 78.6),     # FP64
 }
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def timed_apply(F, g, u, ws, prec, steps, warmup):
+    """Warmup, then `steps` timed applies bracketed by device synchronisation."""
+    import torch
+    for _ in range(warmup):
+        F.apply(g, out=u, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    inf = F.info()
+    F.profile_begin(steps * (4 + 2 * max(inf.depth, 8)) + 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.apply(g, out=u, prec=prec, workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, F.profile_end()
+
+
+def roofline(recs, steps, prec):
+    stage = [r for r in recs if r["kind"] == 1]
+    st_ms = sum(r["ms"] for r in stage)
+    st_flops = sum(r["flops"] for r in stage)
+    st_bytes = sum(r["bytes"] for r in stage)
+    bound, peak = PEAK[prec]
+    mult = 3.0 if prec == "bf16x3" else 1.0  # hi*hi + hi*lo + lo*hi executed
+    achieved = mult * st_flops / (st_ms * 1e-3) / 1e12 if st_ms > 0 else 0.0
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "stage block product", "launches": len(stage),
+            "avg_launch_ms": round(st_ms / max(len(stage), 1), 4),
+            "alg_flops_per_launch_avg": st_flops / max(len(stage), 1),
+            "alg_flops_per_step": st_flops / steps, "executed_flops_factor": mult,
+            "alg_bytes_per_step": st_bytes / steps,
+            "alg_hbm_gbps": round(st_bytes / (st_ms * 1e-3) / 1e9, 1) if st_ms > 0 else 0.0,
+            "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default=DEFAULT_CONFIG, choices=sorted(CONFIGS))
-    ap.add_argument("--prec", default="c64", choices=["c64", "bf16x3", "c128"])
+    ap.add_argument("--save", default=None, help="save the built factors (FP32 + split) to this file")
+    ap.add_argument("--load", default=None, help="load factors saved with --save instead of building")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: multi-GPU runs are not part of this build "
@@ -69,91 +109,128 @@ def main():
     n, nrhs = cfg["n"], cfg["nrhs"]
     N = n * n
     dev = torch.device("cuda:0")
-    if cfg["kernel"] == "dft":
-        x, xi = W.grid_x_integer(n), W.grid_omega(n)
-    else:
-        x, xi = W.grid_x_unit(n), W.grid_omega(n)
-    precs = [args.prec] + ([] if args.no_fp64_check or args.prec == "c128" else ["c128"])
-    log("[bench] building %s (n=%d tol=%g leaf=%d) precs=%s" % (args.config, n, cfg["tol"], cfg["leaf"], precs))
+    x, xi = (W.grid_x_integer(n), W.grid_omega(n)) if cfg["kernel"] == "dft" else (W.grid_x_unit(n), W.grid_omega(n))
+    precs = ["c64"] + ([] if args.no_split else ["bf16x3"])
     t0 = time.time()
-    F = mbf.Factor.build(x, xi, n, kernel=cfg["kernel"], tol=cfg["tol"], leaf_side=cfg["leaf"],
-                         split=cfg["split"], precs=precs, max_rank=4096)
-    build_s = time.time() - t0
+    if args.load:
+        log("loading", args.load)
+        F = mbf.Factor.load(args.load, precs=precs)
+        built = False
+    else:
+        # the FP64 copy is left out when saving (the file keeps FP32 + split only)
+        all_precs = precs + ([] if (args.no_fp64_check or args.save) else ["c128"])
+        log("building %s (n=%d tol=%g leaf=%d) precs=%s" % (args.config, n, cfg["tol"], cfg["leaf"], all_precs))
+        F = mbf.Factor.build(x, xi, n, kernel=cfg["kernel"], tol=cfg["tol"], leaf_side=cfg["leaf"],
+                             split=cfg["split"], precs=all_precs, max_rank=4096)
+        built = True
+    setup_s = time.time() - t0
     inf = F.info()
-    log("[bench] build %.1fs nnz=%.3e depth=%d ranks=%s device GB=%.2f" % (
-        build_s, inf.nnz, inf.depth, list(inf.max_rank[:inf.depth + 1]), inf.device_bytes / 1e9))
+    log("setup %.1fs nnz=%.3e depth=%d ranks=%s device GB=%.2f" % (
+        setup_s, inf.nnz, inf.depth, list(inf.max_rank[:inf.depth + 1]), inf.device_bytes / 1e9))
+    if args.save and built:
+        t1 = time.time()
+        F.save(args.save)
+        log("saved %s in %.1fs" % (args.save, time.time() - t1))
 
     g_host = W.rhs(N, nrhs, seed=0)
-    vdt = torch.complex128 if args.prec == "c128" else torch.complex64
-    g = torch.from_numpy(np.ascontiguousarray(g_host.T)).to(dev, vdt).t()
-    u = torch.empty((nrhs, N), dtype=vdt, device=dev).t()
-    ws = torch.empty(F.workspace_size(args.prec, nrhs), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
+    g = torch.from_numpy(np.ascontiguousarray(g_host.T)).to(dev, torch.complex64).t()
+    u = torch.empty((nrhs, N), dtype=torch.complex64, device=dev).t()
+    ws = torch.empty(max(F.workspace_size("c64", nrhs), F.workspace_size("bf16x3", nrhs) if "bf16x3" in precs else 0),
+                     dtype=torch.uint8, device=dev)
 
-    for _ in range(args.warmup):
-        F.apply(g, out=u, prec=args.prec, workspace=ws)
-    torch.cuda.synchronize()
-    nl = 4 + 2 * inf.depth if inf.depth else 256
-    F.profile_begin(args.steps * nl + 16)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        F.apply(g, out=u, prec=args.prec, workspace=ws, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    recs = F.profile_end()
-    total_s = t1 - t0
+    total_s, recs = timed_apply(F, g, u, ws, "c64", args.steps, args.warmup)
     ms_per_step = 1e3 * total_s / args.steps
     value = nrhs * args.steps / total_s
-
-    stage = [r for r in recs if r["kind"] == 1]
-    st_ms = sum(r["ms"] for r in stage)
-    st_flops = sum(r["flops"] for r in stage)
-    st_bytes = sum(r["bytes"] for r in stage)
-    n_launch = len(stage)
-    bound, peak, unit = PEAK[args.prec]
-    exec_mult = 3.0 if args.prec == "bf16x3" else 1.0  # hi*hi + hi*lo + lo*hi
-    achieved = exec_mult * st_flops / (st_ms * 1e-3) / 1e12 if st_ms > 0 else 0.0
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "stage block product", "launches": n_launch,
-                "avg_launch_ms": round(st_ms / max(n_launch, 1), 4),
-                "alg_flops_per_step": st_flops / args.steps,
-                "alg_bytes_per_step": st_bytes / args.steps,
-                "hbm_gbps_alg": round(st_bytes / (st_ms * 1e-3) / 1e9, 1) if st_ms > 0 else 0.0,
-                "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
+    log("FP32: %.1f RHS/s (%.3f ms/step)" % (value, ms_per_step))
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None,
-           "dtype": {"c64": "f32", "bf16x3": "bf16x3-f32acc", "c128": "f64"}[args.prec],
-           "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "dft2d_n%d_tol%g_leaf%dx%d_rhs%d" % (n, cfg["tol"], cfg["leaf"], cfg["leaf"], nrhs),
                       "kernel": cfg["kernel"], "n": n, "N": N, "nrhs": nrhs, "tol": cfg["tol"],
                       "depth": inf.depth, "ranks": list(inf.max_rank[:inf.depth + 1]), "nnz": inf.nnz,
-                      "factor_gb": round(inf.device_bytes / 1e9, 3), "build_s": round(build_s, 1),
-                      "prec": args.prec},
-           "roofline": roofline}
+                      "factor_gb_on_device": round(inf.device_bytes / 1e9, 3),
+                      "setup_s": round(setup_s, 1), "setup": "load" if args.load else "mbf_build (host FP64)"},
+           "roofline": roofline(recs, args.steps, "c64")}
 
-    # Arithmetic error: same factors, FP64 instantiation on the GPU.
-    u_np = None
-    if "c128" in precs and args.prec != "c128":
+    u32 = u.clone()
+    if not args.no_split:
+        u16 = torch.empty_like(u)
+        s_total, s_recs = timed_apply(F, g, u16, ws, "bf16x3", args.steps, args.warmup)
+        sval = nrhs * args.steps / s_total
+        d = (u16.to(torch.complex128) - u32.to(torch.complex128)).abs().pow(2).sum().sqrt() / \
+            u32.to(torch.complex128).abs().pow(2).sum().sqrt()
+        out["split_bf16x3"] = {"value": round(sval, 2), "unit": "RHS/s", "ms_per_step": round(1e3 * s_total / args.steps, 4),
+                               "dtype": "bf16 hi/lo x3, f32 accumulate", "roofline": roofline(s_recs, args.steps, "bf16x3"),
+                               "rel_diff_vs_fp32_apply": float(d)}
+        log("BF16x3: %.1f RHS/s" % sval)
+        del u16
+
+    if built and not args.no_fp64_check:
         g64 = torch.from_numpy(np.ascontiguousarray(g_host.T)).to(dev, torch.complex128).t()
         u64 = F.apply(g64, prec="c128")
         torch.cuda.synchronize()
-        d = (u.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / u64.abs().pow(2).sum().sqrt()
-        out["rel_err_vs_fp64_apply"] = float(d)
+        nrm = u64.abs().pow(2).sum().sqrt()
+        out["rel_err_vs_fp64_apply"] = float((u32.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
+        if "split_bf16x3" in out:
+            u16 = F.apply(g, prec="bf16x3")
+            torch.cuda.synchronize()
+            out["split_bf16x3"]["rel_err_vs_fp64_apply"] = float(
+                (u16.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
+            del u16
         del g64, u64
-    u_np = u.t().contiguous().cpu().numpy().astype(np.complex128).T
+        torch.cuda.empty_cache()
 
+    if not args.no_serve:
+        out["serving"] = serve_mix(F, N, dev)
+
+    u_np = u32.t().contiguous().cpu().numpy().astype(np.complex128).T
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, x, xi, g_host, u_np, out)
     print(json.dumps(out), flush=True)
 
 
+def serve_mix(F, N, dev, nreq=400, seed=0):
+    """Poisson stream of requests with 1..32 RHS on the resident factorization:
+    continuous batching through mbf_server; offered load ~80% of the measured
+    batched throughput."""
+    import numpy as np
+    import torch
+
+    import mbf_workloads as W
+    import paper_1509_07925_amd as mbf
+
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(1, 33, size=nreq)
+    pool = torch.randn((64, N), dtype=torch.complex64, device=dev)  # request inputs drawn from here
+    outs = [torch.empty((int(k), N), dtype=torch.complex64, device=dev).t() for k in sizes]
+    ins = [pool[: int(k)].t() for k in sizes]
+    # offered load from a solo 32-RHS apply
+    t0 = time.perf_counter()
+    for _ in range(3):
+        F.apply(ins[0] if sizes[0] == 32 else pool[:32].t())
+    torch.cuda.synchronize()
+    per_rhs = (time.perf_counter() - t0) / (3 * 32)
+    rate = 0.8 / (per_rhs * float(np.mean(sizes)))
+    arrivals = W.poisson_arrivals(nreq, rate, seed=seed)
+    srv = mbf.Server(mem_budget=24 << 30, nslots=4, max_batch_rhs=256)
+    t_start = time.perf_counter()
+    for i in range(nreq):
+        while time.perf_counter() - t_start < arrivals[i]:
+            pass
+        srv.submit(F, ins[i], outs[i])
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    return {"requests": int(st["requests"]), "rhs": int(st["rhs"]), "batches": int(st["batches"]),
+            "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+            "rhs_per_s": round(st["rhs"] / st["wall_s"], 1) if st["wall_s"] > 0 else None,
+            "offered_rhs_per_s": round(rate * float(np.mean(sizes)), 1),
+            "max_concurrent_batches": int(st["max_concurrent_batches"])}
+
+
 def cpu_baseline(cfg, x, xi, g, u_gpu, out):
     """Oracle leg: direct FP64 summation (eq. (kernel)) on sampled rows."""
-    import numpy as np
     import threadpoolctl
 
     import mbf_workloads as W
@@ -162,7 +239,7 @@ def cpu_baseline(cfg, x, xi, g, u_gpu, out):
     n, nrhs = cfg["n"], g.shape[1]
     N = n * n
     K = kernels.dft(n) if cfg["kernel"] == "dft" else kernels.fio_radon(n)
-    # bounded sample: about 10-30 s of host work at n = 512
+    # bounded sample: about 10 s of host work at n = 512
     nrows = max(64, min(N, int(4096 * (256.0 / n) ** 2)))
     rows = W.sample_rows(N, nrows, seed=1)
     info = threadpoolctl.threadpool_info()
@@ -170,9 +247,8 @@ def cpu_baseline(cfg, x, xi, g, u_gpu, out):
     t0 = time.perf_counter()
     ref = direct.direct_rows(K, x, xi, g, rows, block=256)
     dt = time.perf_counter() - t0
-    rhs_per_s = nrhs / (dt * N / nrows)
     out["rel_err_vs_direct_sampled_rows"] = direct.rel_err(u_gpu[rows], ref)
-    return {"value": round(rhs_per_s, 6), "unit": "RHS/s", "cores": int(cores), "kind": "oracle",
+    return {"value": round(nrhs / (dt * N / nrows), 6), "unit": "RHS/s", "cores": int(cores), "kind": "oracle",
             "sample": "direct FP64 sum of eq. (kernel) on %d of %d rows x %d RHS in %.2f s, "
                       "scaled to the full N" % (nrows, N, nrhs, dt)}
 

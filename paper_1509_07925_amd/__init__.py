@@ -75,7 +75,7 @@ EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
            "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
            "mbf_server_submit", "mbf_server_poll", "mbf_server_drain", "mbf_server_stats",
-           "mbf_server_destroy"]
+           "mbf_server_destroy", "mbf_save", "mbf_load"]
 
 
 def lib():
@@ -105,13 +105,15 @@ def lib():
     L.mbf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.mbf_server_destroy.argtypes = [vp]
     L.mbf_server_destroy.restype = None
+    L.mbf_save.argtypes = [vp, ctypes.c_char_p]
+    L.mbf_load.argtypes = [ctypes.c_char_p, u32, vp, ctypes.POINTER(vp)]
     L.mbf_destroy.argtypes = [vp]
     L.mbf_destroy.restype = None
     L.mbf_last_error.restype = ctypes.c_char_p
     for name in ("mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
                  "mbf_apply_adjoint", "mbf_info", "mbf_profile_begin", "mbf_profile_end",
                  "mbf_server_create", "mbf_server_submit", "mbf_server_poll", "mbf_server_drain",
-                 "mbf_server_stats"):
+                 "mbf_server_stats", "mbf_save", "mbf_load"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -207,6 +209,17 @@ class Factor:
         _check(L.mbf_build(2, x.shape[0], x.ctypes.data, xi.shape[0], xi.ctypes.data, cb, user,
                            ctypes.byref(o), None, ctypes.byref(h)))
         return cls(h)
+
+    @classmethod
+    def load(cls, path, precs=()):
+        """mbf_load: a factorization saved by ``save`` (precs=() keeps all stored)."""
+        h = ctypes.c_void_p()
+        _check(lib().mbf_load(os.fsencode(path), _mask(precs), None, ctypes.byref(h)))
+        return cls(h)
+
+    def save(self, path):
+        """mbf_save: write every precision held on the device to ``path``."""
+        _check(lib().mbf_save(self._h, os.fsencode(path)))
 
     # ------------------------------------------------------------ queries
     def info(self):

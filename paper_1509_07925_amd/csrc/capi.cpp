@@ -216,6 +216,28 @@ mbf_status mbf_multiscale_assemble(int32_t nparts, mbf_factor* parts, const int6
   });
 }
 
+mbf_status mbf_save(mbf_factor f, const char* path) {
+  if (!f || !path) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
+  return guarded([&]() -> mbf_status { return from(save_factor(f->dev, path)); });
+}
+
+mbf_status mbf_load(const char* path, uint32_t prec_mask, void* stream, mbf_factor* out) {
+  (void)stream;
+  if (!path || !out) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
+  *out = nullptr;
+  return guarded([&]() -> mbf_status {
+    auto* h = new mbf_factor_s();
+    Error e = load_factor(path, prec_mask & ((1u << kNumPrec) - 1), h->dev);
+    if (e.st != MBF_OK) {
+      free_factor(h->dev);
+      delete h;
+      return from(e);
+    }
+    *out = h;
+    return MBF_OK;
+  });
+}
+
 mbf_status mbf_workspace_size(mbf_factor f, mbf_prec p, int64_t nrhs, size_t* bytes) {
   if (!f || !bytes || nrhs < 0 || !valid_prec(p)) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
   *bytes = workspace_bytes(f->dev, p, nrhs);

@@ -98,6 +98,9 @@ Error upload_center(DevFactor& F, const std::vector<cd>& KC, const std::vector<i
                     uint32_t prec_mask);
 void free_factor(DevFactor& F);
 
+Error save_factor(const DevFactor& F, const char* path);
+Error load_factor(const char* path, uint32_t prec_mask, DevFactor& F);
+
 size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs);
 Error launch_apply(const DevFactor& F, int prec, bool adjoint, int64_t nrhs, const void* in,
                    int64_t ldin, void* out, int64_t ldout, void* ws, size_t ws_bytes,

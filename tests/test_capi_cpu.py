@@ -82,3 +82,19 @@ def test_builtin_kernels_match_oracle_definitions(n):
     xu = W.grid_x_unit(n)
     got = _call_kernel("mbf_kernel_fio", n, xu, xi, rows, cols)
     np.testing.assert_allclose(got, kernels.fio_radon(n)(xu[rows], xi[cols]), atol=1e-11)
+
+
+def test_load_rejects_missing_and_corrupted_files(tmp_path):
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.load(str(tmp_path / "missing.mbf"))
+    assert e.value.status == -7
+    bad = tmp_path / "bad.mbf"
+    bad.write_bytes(b"not a factor file at all")
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.load(str(bad))
+    assert e.value.status == -7
+    wrongver = tmp_path / "ver.mbf"
+    wrongver.write_bytes(b"MBFFACT1" + (99).to_bytes(4, "little") + bytes(40))
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.load(str(wrongver))
+    assert "version" in str(e.value)

@@ -199,3 +199,24 @@ def test_matrix_core_polar_ragged_bf16x3():
     F = _import(bf, ["bf16x3", "c64"])
     _check_both(F, bf, n * n, n * n, 70, "bf16x3")
     _check_both(F, bf, n * n, n * n, 70, "c64")
+
+
+def test_save_load_roundtrip_is_bit_exact(tmp_path):
+    n = 32
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    bf = butterfly.build_polar(kernels.fio_radon(n), x, xi, n, ((0, 0), 1.0), 4, 1e-6, 10 ** 6)
+    F = _import(bf, ["c64", "c128"])
+    path = str(tmp_path / "f.mbf")
+    F.save(path)
+    G = _mbf().Factor.load(path, precs=["c64"])
+    g = W.rhs(n * n, 40, seed=21)
+    a = _from_gpu(F.apply(_to_gpu(g, "c64")))
+    b = _from_gpu(G.apply(_to_gpu(g, "c64")))
+    np.testing.assert_array_equal(a, b)
+    with pytest.raises(_mbf().MBFError):
+        G.apply(_to_gpu(g, "c128"), prec="c128")  # not loaded
+    # truncated file
+    data = open(path, "rb").read()
+    open(path, "wb").write(data[: len(data) // 2])
+    with pytest.raises(_mbf().MBFError):
+        _mbf().Factor.load(path)
