@@ -87,7 +87,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default=DEFAULT_CONFIG, choices=sorted(CONFIGS))
-    ap.add_argument("--save", default=None, help="save the built factors (FP32 + split) to this file")
+    ap.add_argument("--save", default=None, help="save the built factors to this file")
+    ap.add_argument("--save-precs", default="c64,bf16x3", help="precisions written by --save")
     ap.add_argument("--load", default=None, help="load factors saved with --save instead of building")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
@@ -117,8 +118,7 @@ def main():
         F = mbf.Factor.load(args.load, precs=precs)
         built = False
     else:
-        # the FP64 copy is left out when saving (the file keeps FP32 + split only)
-        all_precs = precs + ([] if (args.no_fp64_check or args.save) else ["c128"])
+        all_precs = precs + ([] if args.no_fp64_check else ["c128"])
         log("building %s (n=%d tol=%g leaf=%d) precs=%s" % (args.config, n, cfg["tol"], cfg["leaf"], all_precs))
         F = mbf.Factor.build(x, xi, n, kernel=cfg["kernel"], tol=cfg["tol"], leaf_side=cfg["leaf"],
                              split=cfg["split"], precs=all_precs, max_rank=4096)
@@ -129,7 +129,7 @@ def main():
         setup_s, inf.nnz, inf.depth, list(inf.max_rank[:inf.depth + 1]), inf.device_bytes / 1e9))
     if args.save and built:
         t1 = time.time()
-        F.save(args.save)
+        F.save(args.save, precs=[p for p in args.save_precs.split(",") if p])
         log("saved %s in %.1fs" % (args.save, time.time() - t1))
 
     g_host = W.rhs(N, nrhs, seed=0)

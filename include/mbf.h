@@ -194,14 +194,14 @@ mbf_status mbf_multiscale_assemble(int32_t nparts, mbf_factor* parts, const int6
                                    const int64_t* center_idx, const double* center,
                                    uint32_t prec_mask, void* stream, mbf_factor* out);
 
-/* Checkpoint / resume of built factorizations.  mbf_save writes every
- * precision the handle holds to a versioned binary file (device -> host in
- * chunks; synchronous).  mbf_load reads it back onto the current device,
+/* Checkpoint / resume of built factorizations.  mbf_save writes the
+ * precisions in prec_mask (0 = every precision the handle holds) to a
+ * versioned binary file (device -> host in chunks; synchronous).  mbf_load reads it back onto the current device,
  * keeping the precisions in prec_mask (0 = all stored).  Errors: MBF_ERR_IO
  * (cannot open, write failure, wrong magic / version, corrupted or
  * truncated file: nothing is left allocated), MBF_ERR_UNSUPPORTED (a
  * requested precision is not in the file), MBF_ERR_OOM. */
-mbf_status mbf_save(mbf_factor f, const char* path);
+mbf_status mbf_save(mbf_factor f, uint32_t prec_mask, const char* path);
 mbf_status mbf_load(const char* path, uint32_t prec_mask, void* stream, mbf_factor* out);
 
 /* Bytes of device workspace needed by an apply of nrhs columns. */

@@ -105,7 +105,7 @@ def lib():
     L.mbf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.mbf_server_destroy.argtypes = [vp]
     L.mbf_server_destroy.restype = None
-    L.mbf_save.argtypes = [vp, ctypes.c_char_p]
+    L.mbf_save.argtypes = [vp, u32, ctypes.c_char_p]
     L.mbf_load.argtypes = [ctypes.c_char_p, u32, vp, ctypes.POINTER(vp)]
     L.mbf_destroy.argtypes = [vp]
     L.mbf_destroy.restype = None
@@ -217,9 +217,9 @@ class Factor:
         _check(lib().mbf_load(os.fsencode(path), _mask(precs), None, ctypes.byref(h)))
         return cls(h)
 
-    def save(self, path):
-        """mbf_save: write every precision held on the device to ``path``."""
-        _check(lib().mbf_save(self._h, os.fsencode(path)))
+    def save(self, path, precs=()):
+        """mbf_save: write the given precisions (default: all held) to ``path``."""
+        _check(lib().mbf_save(self._h, _mask(precs), os.fsencode(path)))
 
     # ------------------------------------------------------------ queries
     def info(self):

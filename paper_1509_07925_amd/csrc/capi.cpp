@@ -216,9 +216,12 @@ mbf_status mbf_multiscale_assemble(int32_t nparts, mbf_factor* parts, const int6
   });
 }
 
-mbf_status mbf_save(mbf_factor f, const char* path) {
+mbf_status mbf_save(mbf_factor f, uint32_t prec_mask, const char* path) {
   if (!f || !path) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
-  return guarded([&]() -> mbf_status { return from(save_factor(f->dev, path)); });
+  prec_mask &= (1u << kNumPrec) - 1;
+  if (prec_mask == 0) prec_mask = f->dev.prec_mask;
+  if ((prec_mask & f->dev.prec_mask) != prec_mask) return fail(MBF_ERR_UNSUPPORTED, "precision not held by the factor");
+  return guarded([&]() -> mbf_status { return from(save_factor(f->dev, prec_mask, path)); });
 }
 
 mbf_status mbf_load(const char* path, uint32_t prec_mask, void* stream, mbf_factor* out) {

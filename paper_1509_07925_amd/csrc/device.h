@@ -98,7 +98,7 @@ Error upload_center(DevFactor& F, const std::vector<cd>& KC, const std::vector<i
                     uint32_t prec_mask);
 void free_factor(DevFactor& F);
 
-Error save_factor(const DevFactor& F, const char* path);
+Error save_factor(const DevFactor& F, uint32_t prec_mask, const char* path);
 Error load_factor(const char* path, uint32_t prec_mask, DevFactor& F);
 
 size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs);

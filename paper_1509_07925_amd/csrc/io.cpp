@@ -103,13 +103,13 @@ size_t real_elem(int p) { return p == MBF_C128 ? 8 : 4; }
 
 }  // namespace
 
-Error save_factor(const DevFactor& D, const char* path) {
+Error save_factor(const DevFactor& D, uint32_t mask, const char* path) {
   File F;
   F.f = std::fopen(path, "wb");
   if (!F.f) return {MBF_ERR_IO, std::string("cannot open ") + path};
   F.w(kMagic, 8);
   F.w(&kVersion, 4);
-  F.w(&D.prec_mask, 4);
+  F.w(&mask, 4);
   F.w(&D.nx, 8);
   F.w(&D.nxi, 8);
   F.w(&D.n_center, 8);
@@ -136,7 +136,7 @@ Error save_factor(const DevFactor& D, const char* path) {
         !dev_to_file(F, P.d_uidx, P.nx * 4))
       return {MBF_ERR_IO, "write failed"};
     for (int p = 0; p < kNumPrec; ++p) {
-      if (!(D.prec_mask & (1u << p))) continue;
+      if (!(mask & (1u << p))) continue;
       const PrecData& d = P.prec[p];
       if (!dev_to_file(F, d.W, P.w_elems * elem(p)) || !dev_to_file(F, d.V0, P.v_elems * leaf_elem(p)) ||
           !dev_to_file(F, d.UL, P.u_elems * leaf_elem(p)) || !dev_to_file(F, d.S, P.s_elems * real_elem(p)))
@@ -146,7 +146,7 @@ Error save_factor(const DevFactor& D, const char* path) {
   if (D.n_center > 0) {
     if (!dev_to_file(F, D.d_center_idx, D.n_center * 4)) return {MBF_ERR_IO, "write failed"};
     for (int p = 0; p < kNumPrec; ++p)
-      if (D.prec_mask & (1u << p))
+      if (mask & (1u << p))
         if (!dev_to_file(F, D.center[p].center, (size_t)D.nx * D.n_center * leaf_elem(p)))
           return {MBF_ERR_IO, "write failed"};
   }
