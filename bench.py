@@ -94,7 +94,18 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: multi-GPU runs are not part of this build "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
