@@ -81,6 +81,21 @@ def roofline(recs, steps, prec):
             "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
 
 
+def measured_traffic(workload, prec):
+    """HBM bytes per stage launch from the committed rocprofv3 counter runs
+    (profiles/hbm_traffic_*.json), or None when those counters were taken
+    on another workload / precision or before the stage kernel last changed."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1509_07925_amd", "csrc", "stage_mfma.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
+        rec = json.load(open(path))
+        if rec.get("workload") == workload and rec.get("prec") == prec and rec.get("kernel_source_sha256_16") == sha:
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +178,7 @@ def main():
                       "factor_gb_on_device": round(inf.device_bytes / 1e9, 3),
                       "setup_s": round(setup_s, 1), "setup": "load" if args.load else "mbf_build (host FP64)"},
            "roofline": roofline(recs, args.steps, "c64")}
+    out["roofline"]["traffic"] = measured_traffic(out["config"]["workload"], "c64")
 
     u32 = u.clone()
     if not args.no_split:
