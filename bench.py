@@ -164,6 +164,11 @@ def main():
     ws = torch.empty(max(F.workspace_size("c64", nrhs), F.workspace_size("bf16x3", nrhs) if "bf16x3" in precs else 0),
                      dtype=torch.uint8, device=dev)
 
+    t1 = time.time()
+    tuned = F.autotune("c64", nrhs, workspace=ws)
+    if "bf16x3" in precs:
+        tuned += F.autotune("bf16x3", nrhs, workspace=ws)
+    log("autotuned %d stage shapes in %.1fs" % (tuned, time.time() - t1))
     total_s, recs = timed_apply(F, g, u, ws, "c64", args.steps, args.warmup)
     ms_per_step = 1e3 * total_s / args.steps
     value = nrhs * args.steps / total_s

@@ -235,6 +235,18 @@ typedef struct {
 } mbf_info_t;
 mbf_status mbf_info(mbf_factor f, mbf_info_t* out);
 
+/* Autotuner of the stage kernels: for every stage shape of f at this
+ * precision and RHS count, times each stage-kernel variant (reduction chunk
+ * 16 / 32 complex entries, register prefetch off / on) on scratch data in
+ * `workspace` (overwritten; same size as for mbf_apply), forward and
+ * adjoint, and keeps the fastest for all later applies of that shape in
+ * this process.  When the environment variable MBF_TUNE_FILE names a file,
+ * choices are appended to it and read back by later processes.  Waits for
+ * its own launches (synchronizes `stream`).  *tuned = stage shapes timed.
+ * Applies without tuning use a fixed default variant. */
+mbf_status mbf_autotune(mbf_factor f, mbf_prec p, int64_t nrhs, void* workspace, size_t ws_bytes, void* stream,
+                        int32_t* tuned);
+
 /* Per-launch timing of the apply kernels with HIP events (instrumentation,
  * Section 2.5: cost per factor).  mbf_profile_begin creates 2 * max_launches
  * events (it may allocate; call it outside graph capture and timed loops).

@@ -75,7 +75,7 @@ EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
            "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
            "mbf_server_submit", "mbf_server_poll", "mbf_server_drain", "mbf_server_stats",
-           "mbf_server_destroy", "mbf_save", "mbf_load"]
+           "mbf_server_destroy", "mbf_save", "mbf_load", "mbf_autotune"]
 
 
 def lib():
@@ -106,6 +106,7 @@ def lib():
     L.mbf_server_destroy.argtypes = [vp]
     L.mbf_server_destroy.restype = None
     L.mbf_save.argtypes = [vp, u32, ctypes.c_char_p]
+    L.mbf_autotune.argtypes = [vp, i32, i64, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32)]
     L.mbf_load.argtypes = [ctypes.c_char_p, u32, vp, ctypes.POINTER(vp)]
     L.mbf_destroy.argtypes = [vp]
     L.mbf_destroy.restype = None
@@ -113,7 +114,7 @@ def lib():
     for name in ("mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
                  "mbf_apply_adjoint", "mbf_info", "mbf_profile_begin", "mbf_profile_end",
                  "mbf_server_create", "mbf_server_submit", "mbf_server_poll", "mbf_server_drain",
-                 "mbf_server_stats", "mbf_save", "mbf_load"):
+                 "mbf_server_stats", "mbf_save", "mbf_load", "mbf_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -268,6 +269,17 @@ class Factor:
     def apply_adjoint(self, h, out=None, prec="c64", workspace=None, stream=None):
         """v = K^* h (mbf_apply_adjoint)."""
         return self._run(True, h, out, prec, workspace, stream)
+
+    def autotune(self, prec="c64", nrhs=256, workspace=None, stream=None):
+        """mbf_autotune: time the stage-kernel variants for this RHS count; returns shapes tuned."""
+        import torch
+        need = self.workspace_size(prec, nrhs)
+        if workspace is None or workspace.numel() * workspace.element_size() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        n = ctypes.c_int32()
+        _check(lib().mbf_autotune(self._h, PREC[prec], nrhs, ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel() * workspace.element_size(), _stream_ptr(stream), ctypes.byref(n)))
+        return n.value
 
     def profile_begin(self, max_launches):
         _check(lib().mbf_profile_begin(self._h, max_launches))

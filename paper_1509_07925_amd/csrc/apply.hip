@@ -525,6 +525,33 @@ int64_t state_ld_max(const DevFactor& F) {
 
 }  // namespace
 
+Error autotune_factor(const DevFactor& F, int prec, int64_t nrhs, void* ws, size_t ws_bytes, hipStream_t st,
+                      int* ntuned) {
+  if (ws_bytes < workspace_bytes(F, prec, nrhs)) return {MBF_ERR_INVALID_ARG, "workspace too small"};
+  if (ntuned) *ntuned = 0;
+  if (prec == MBF_C128) return {MBF_OK, ""};
+  const int64_t ws_ld = state_ld_max(F);
+  if (hipMemsetAsync(ws, 0, 2 * (size_t)ws_ld * nrhs * 8, st) != hipSuccess) return {MBF_ERR_HIP, "memset"};
+  for (const auto& P : F.parts) {
+    char* b0 = reinterpret_cast<char*>(ws);
+    char* b1 = b0 + (size_t)ws_ld * nrhs * 8;
+    char* buf[2] = {b0, b1};
+    for (int s = 0; s < P.L; ++s) {
+      if (P.nblk[s] == 0 || !use_mfma(P, s, nrhs, prec)) continue;
+      const BlockDesc* bd = P.d_blk + P.blk_first[s];
+      for (int adj = 0; adj < 2; ++adj) {
+        Error e = adj ? autotune_stage(P, s, prec, true, bd, P.prec[prec].W, buf[(s + 1) & 1], P.ld[s + 1],
+                                       buf[s & 1], P.ld[s], (int)nrhs, st, nullptr, nullptr)
+                      : autotune_stage(P, s, prec, false, bd, P.prec[prec].W, buf[s & 1], P.ld[s],
+                                       buf[(s + 1) & 1], P.ld[s + 1], (int)nrhs, st, nullptr, nullptr);
+        if (e.st != MBF_OK) return e;
+        if (ntuned) ++*ntuned;
+      }
+    }
+  }
+  return {MBF_OK, ""};
+}
+
 size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs) {
   const size_t es = prec == MBF_C128 ? 16 : 8;
   size_t b = 2 * (size_t)state_ld_max(F) * (size_t)nrhs * es;

@@ -216,6 +216,16 @@ mbf_status mbf_multiscale_assemble(int32_t nparts, mbf_factor* parts, const int6
   });
 }
 
+mbf_status mbf_autotune(mbf_factor f, mbf_prec p, int64_t nrhs, void* workspace, size_t ws_bytes, void* stream,
+                        int32_t* tuned) {
+  if (!f || !valid_prec(p) || nrhs <= 0 || !workspace) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
+  if (!(f->dev.prec_mask & (1u << p))) return fail(MBF_ERR_UNSUPPORTED, "precision not built for this factor");
+  int n = 0;
+  mbf_status st = from(autotune_factor(f->dev, p, nrhs, workspace, ws_bytes, (hipStream_t)stream, &n));
+  if (tuned) *tuned = n;
+  return st;
+}
+
 mbf_status mbf_save(mbf_factor f, uint32_t prec_mask, const char* path) {
   if (!f || !path) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
   prec_mask &= (1u << kNumPrec) - 1;

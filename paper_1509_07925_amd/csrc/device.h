@@ -102,6 +102,8 @@ Error save_factor(const DevFactor& F, uint32_t prec_mask, const char* path);
 Error load_factor(const char* path, uint32_t prec_mask, DevFactor& F);
 
 size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs);
+Error autotune_factor(const DevFactor& F, int prec, int64_t nrhs, void* ws, size_t ws_bytes, hipStream_t st,
+                      int* ntuned);
 Error launch_apply(const DevFactor& F, int prec, bool adjoint, int64_t nrhs, const void* in,
                    int64_t ldin, void* out, int64_t ldout, void* ws, size_t ws_bytes,
                    hipStream_t stream);

@@ -12,8 +12,21 @@ namespace mbf {
 // the split layout).
 bool use_mfma(const DevPart& P, int s, int64_t nrhs, int prec);
 
+// Stage kernel variants (reduction chunk 16 / 32, register prefetch off / on).
+constexpr int kNumVariants = 4;
+
+// force_variant >= 0 bypasses the tuned choice.
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adjoint, const BlockDesc* blk,
                         const void* W, const void* in, int64_t ld_in, void* out, int64_t ld_out,
-                        int nrhs, const float* scale, hipStream_t st);
+                        int nrhs, const float* scale, hipStream_t st, int force_variant = -1);
+
+// Variant used for a stage shape (tuned, else MBF_STAGE_VARIANT, else a default).
+int tuned_variant(int prec, bool adj, int R, int Q, int nrhs);
+
+// Time every variant on stage s (2 launches each after one warm-up launch,
+// on scratch data in / out) and record the fastest for the shape.
+Error autotune_stage(const DevPart& P, int s, int prec, bool adj, const BlockDesc* blk, const void* W,
+                     const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs, hipStream_t st,
+                     int* chosen, float* best_ms);
 
 }  // namespace mbf

@@ -24,7 +24,12 @@
 // block) land on the same XCD so that they share its L2.
 #include "stage_mfma.h"
 
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 namespace mbf {
 
@@ -35,7 +40,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int TN = 64;   // right-hand sides per tile
 constexpr int TM = 64;   // complex output rows per tile
-constexpr int KC = 16;   // complex reduction entries per chunk
 constexpr int kXcd = 8;  // XCDs per device
 
 __device__ __forceinline__ int32_t grp_row(const BlockDesc& d, int32_t i) {
@@ -113,17 +117,67 @@ __device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int
   }
 }
 
+// ------------------------------------------------------------------ loads
+// Each chunk moves a TN x KC tile of the input state (A) and a KC x TM tile
+// of the block (B) into LDS, KC/4 entries per thread, with consecutive lanes
+// on consecutive memory (the reduction index for A and for the adjoint's
+// B, the output index for the forward B).  With PF the registers for the
+// next chunk are loaded while the matrix cores work on the current one.
+template <int KC, bool ADJ, typename WT>
+struct Loader {
+  static constexpr int E = KC / 4;
+  float2 a[E];
+  WT b[E];
+  __device__ __forceinline__ void load(const BlockDesc& d, const float2* __restrict__ in, int64_t ld_in,
+                                       const WT* __restrict__ Wb, int R, int Q, int r0, int n0, int q0,
+                                       int nrhs) {
+    const int tid = threadIdx.x;
+    {  // A(n, k): k = tid % KC, rows tid / KC + j * (256 / KC)
+      const int k = tid % KC, n = tid / KC;
+      const int q = q0 + k;
+      int32_t row = 0;
+      if (q < Q) row = ADJ ? grp_row(d, q) : d.in_row + q;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int gn = n0 + n + j * (256 / KC);
+        float2 v = make_float2(0.f, 0.f);
+        if (gn < nrhs && q < Q) v = in[(int64_t)gn * ld_in + row];
+        a[j] = v;
+      }
+    }
+    if (!ADJ) {  // W(m, k), m contiguous: m = tid % 64, k = tid / 64 + 4 j
+      const int m = r0 + (tid & 63), kb = tid >> 6;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int q = q0 + kb + 4 * j;
+        WT w{};
+        if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
+        b[j] = w;
+      }
+    } else {  // W(m', k'), m' contiguous: m' = tid % KC, k' = tid / KC + j * (256 / KC)
+      const int mr = q0 + tid % KC, kp = tid / KC;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int kout = r0 + kp + j * (256 / KC);
+        WT w{};
+        if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
+        b[j] = w;
+      }
+    }
+  }
+};
+
 // ------------------------------------------------------------------ FP32
-template <bool ADJ>
+template <bool ADJ, int KC, bool PF>
 __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__ blk,
                                                    const float2* __restrict__ W,
                                                    const float2* __restrict__ in, int64_t ld_in,
                                                    float2* __restrict__ out, int64_t ld_out, int nrhs,
                                                    const float* __restrict__ scale, int mtiles, int ntiles,
                                                    int64_t total) {
-  constexpr int PA = KC + 4, PB = KC + 4;
-  __shared__ __attribute__((aligned(16))) float As[2][TN][PA];      // [re|im][n][k]
-  __shared__ __attribute__((aligned(16))) float Bs[2][2 * TM][PB];  // [c][real col][k]
+  constexpr int P = KC + 4;
+  __shared__ __attribute__((aligned(16))) float As[2][TN][P];      // [re|im][n][k]
+  __shared__ __attribute__((aligned(16))) float Bs[2][2 * TM][P];  // [c][real col][k]
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
   const BlockDesc d = blk[tl.b];
@@ -136,54 +190,45 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
   const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
   const float2* Wb = W + d.w_off;
   v16f acc[2], cmp[2];
-  acc[0] = v16f{};
-  acc[1] = v16f{};
-  cmp[0] = v16f{};
-  cmp[1] = v16f{};
+  acc[0] = acc[1] = cmp[0] = cmp[1] = v16f{};
+  Loader<KC, ADJ, float2> ld;
+  if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
-    {  // A: 64 right-hand sides x 16 complex reduction entries
-      const int n = tid >> 2, kq = (tid & 3) * 4;
-      const int gn = n0 + n;
+    if (!PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+    {  // registers -> LDS
+      constexpr int E = KC / 4;
+      const int k = tid % KC, n = tid / KC;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int q = q0 + kq + j;
-        float2 v = make_float2(0.f, 0.f);
-        if (gn < nrhs && q < Q) {
-          const int32_t row = ADJ ? grp_row(d, q) : d.in_row + q;
-          v = in[(int64_t)gn * ld_in + row];
+      for (int j = 0; j < E; ++j) {
+        As[0][n + j * (256 / KC)][k] = ld.a[j].x;
+        As[1][n + j * (256 / KC)][k] = ld.a[j].y;
+      }
+      if (!ADJ) {
+        const int c = 2 * (tid & 63), kb = tid >> 6;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const float2 w = ld.b[j];
+          const int kk = kb + 4 * j;
+          Bs[0][c][kk] = w.x;
+          Bs[0][c + 1][kk] = w.y;
+          Bs[1][c][kk] = -w.y;
+          Bs[1][c + 1][kk] = w.x;
         }
-        As[0][n][kq + j] = v.x;
-        As[1][n][kq + j] = v.y;
-      }
-    }
-    if (!ADJ) {  // B from W(m, k): 16 k x 64 m, m contiguous in memory
-      const int k = tid >> 4, mq = (tid & 15) * 4;
+      } else {
+        const int mr = tid % KC, kp = tid / KC;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = r0 + mq + j, q = q0 + k;
-        float2 w = make_float2(0.f, 0.f);
-        if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
-        const int c = 2 * (mq + j);
-        Bs[0][c][k] = w.x;
-        Bs[0][c + 1][k] = w.y;
-        Bs[1][c][k] = -w.y;
-        Bs[1][c + 1][k] = w.x;
-      }
-    } else {  // B from conj(W(m', k')): 16 m' (reduction) x 64 k' (output), m' contiguous
-      const int kp = tid >> 2, mq = (tid & 3) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kout = r0 + kp, mr = q0 + mq + j;
-        float2 w = make_float2(0.f, 0.f);
-        if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
-        const int c = 2 * kp;
-        Bs[0][c][mq + j] = w.x;
-        Bs[0][c + 1][mq + j] = -w.y;
-        Bs[1][c][mq + j] = w.y;
-        Bs[1][c + 1][mq + j] = w.x;
+        for (int j = 0; j < E; ++j) {
+          const float2 w = ld.b[j];
+          const int c = 2 * (kp + j * (256 / KC));
+          Bs[0][c][mr] = w.x;
+          Bs[0][c + 1][mr] = -w.y;
+          Bs[1][c][mr] = w.y;
+          Bs[1][c + 1][mr] = w.x;
+        }
       }
     }
     __syncthreads();
+    if (PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
     const int kk = lane >> 5, li = lane & 31;
     v16f p0 = v16f{}, p1 = v16f{};
 #pragma unroll
@@ -212,7 +257,7 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
 // ------------------------------------------------------------------ BF16 x3
 // LDS rows hold interleaved pairs along the complex reduction index: entry
 // (row, k) is one 32-bit word = two BF16 values (real-k 2k and 2k+1).
-template <bool ADJ>
+template <bool ADJ, int KC, bool PF>
 __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restrict__ blk,
                                                       const uint2* __restrict__ W,  // (re_hi,im_hi | re_lo,im_lo)
                                                       const float2* __restrict__ in, int64_t ld_in,
@@ -234,61 +279,52 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
   const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
   const uint2* Wb = W + d.w_off;
   v16f acc[2], cmp[2];
-  acc[0] = v16f{};
-  acc[1] = v16f{};
-  cmp[0] = v16f{};
-  cmp[1] = v16f{};
+  acc[0] = acc[1] = cmp[0] = cmp[1] = v16f{};
+  Loader<KC, ADJ, uint2> ld;
+  if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
-    {
-      const int n = tid >> 2, kq = (tid & 3) * 4;
-      const int gn = n0 + n;
+    if (!PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+    {  // registers -> LDS (state split into BF16 hi/lo here)
+      constexpr int E = KC / 4;
+      const int k = tid % KC, n = tid / KC;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int q = q0 + kq + j;
-        float2 v = make_float2(0.f, 0.f);
-        if (gn < nrhs && q < Q) {
-          const int32_t row = ADJ ? grp_row(d, q) : d.in_row + q;
-          v = in[(int64_t)gn * ld_in + row];
-        }
+      for (int j = 0; j < E; ++j) {
         uint32_t rh, rl, ih, il;
-        split_bf(v.x, rh, rl);
-        split_bf(v.y, ih, il);
-        Ah[n][kq + j] = rh | (ih << 16);
-        Al[n][kq + j] = rl | (il << 16);
+        split_bf(ld.a[j].x, rh, rl);
+        split_bf(ld.a[j].y, ih, il);
+        Ah[n + j * (256 / KC)][k] = rh | (ih << 16);
+        Al[n + j * (256 / KC)][k] = rl | (il << 16);
       }
-    }
-    if (!ADJ) {
-      const int k = tid >> 4, mq = (tid & 15) * 4;
+      if (!ADJ) {
+        const int c = 2 * (tid & 63), kb = tid >> 6;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = r0 + mq + j, q = q0 + k;
-        uint2 w = make_uint2(0u, 0u);
-        if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
-        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-        const int c = 2 * (mq + j);
-        // column 2m (real part):      (Wr, -Wi);  column 2m+1 (imag part): (Wi, Wr)
-        Bh[c][k] = reh | ((imh ^ 0x8000u) << 16);
-        Bh[c + 1][k] = imh | (reh << 16);
-        Bl[c][k] = rel | ((iml ^ 0x8000u) << 16);
-        Bl[c + 1][k] = iml | (rel << 16);
-      }
-    } else {
-      const int kp = tid >> 2, mq = (tid & 3) * 4;
+        for (int j = 0; j < E; ++j) {
+          const uint2 w = ld.b[j];
+          const int kk = kb + 4 * j;
+          const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+          // column 2m (real part): (Wr, -Wi);  column 2m+1 (imag part): (Wi, Wr)
+          Bh[c][kk] = reh | ((imh ^ 0x8000u) << 16);
+          Bh[c + 1][kk] = imh | (reh << 16);
+          Bl[c][kk] = rel | ((iml ^ 0x8000u) << 16);
+          Bl[c + 1][kk] = iml | (rel << 16);
+        }
+      } else {
+        const int mr = tid % KC, kp = tid / KC;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kout = r0 + kp, mr = q0 + mq + j;
-        uint2 w = make_uint2(0u, 0u);
-        if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
-        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-        const int c = 2 * kp;
-        // conj(W): column 2k' (real part): (Wr, Wi);  column 2k'+1 (imag part): (-Wi, Wr)
-        Bh[c][mq + j] = reh | (imh << 16);
-        Bh[c + 1][mq + j] = (imh ^ 0x8000u) | (reh << 16);
-        Bl[c][mq + j] = rel | (iml << 16);
-        Bl[c + 1][mq + j] = (iml ^ 0x8000u) | (rel << 16);
+        for (int j = 0; j < E; ++j) {
+          const uint2 w = ld.b[j];
+          const int c = 2 * (kp + j * (256 / KC));
+          const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+          // conj(W): column 2k' (real part): (Wr, Wi);  column 2k'+1 (imag part): (-Wi, Wr)
+          Bh[c][mr] = reh | (imh << 16);
+          Bh[c + 1][mr] = (imh ^ 0x8000u) | (reh << 16);
+          Bl[c][mr] = rel | (iml << 16);
+          Bl[c + 1][mr] = (iml ^ 0x8000u) | (rel << 16);
+        }
       }
     }
     __syncthreads();
+    if (PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
     const int kh = lane >> 5, li = lane & 31;
     v16f part[2] = {v16f{}, v16f{}};
 #pragma unroll
@@ -325,38 +361,153 @@ bool use_mfma(const DevPart&, int, int64_t nrhs, int prec) {
   return false;
 }
 
+// ------------------------------------------------------------------ autotuner
+// Variant choice per (precision, direction, output-rows bucket, reduction
+// bucket, RHS tiles).  Filled by autotune_stage (timing every variant on the
+// stage's real shape) and optionally persisted as text lines
+// "prec adj rb qb nb variant" in the file named by MBF_TUNE_FILE.
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+TuneKey tune_key(int prec, bool adj, int R, int Q, int nrhs) {
+  return TuneKey{prec, adj ? 1 : 0, (R + 63) / 64, (Q + 63) / 64, (nrhs + TN - 1) / TN};
+}
+
+void load_tune_file_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("MBF_TUNE_FILE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int a, b, c, d, e, v;
+  while (std::fscanf(f, "%d %d %d %d %d %d", &a, &b, &c, &d, &e, &v) == 6)
+    if (v >= 0 && v < kNumVariants) g_tune[TuneKey{a, b, c, d, e}] = v;
+  std::fclose(f);
+}
+}  // namespace
+
+int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file_locked();
+  auto it = g_tune.find(tune_key(prec, adj, R, Q, nrhs));
+  if (it != g_tune.end()) return it->second;
+  if (const char* e = std::getenv("MBF_STAGE_VARIANT")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && v < kNumVariants) return v;
+  }
+  return prec == MBF_C64 ? 0 : 3;
+}
+
+// Kernel variants: (reduction chunk, register prefetch).  variant index:
+//   0 = (16, off)  1 = (16, on)  2 = (32, off)  3 = (32, on)
+template <bool ADJ>
+static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const BlockDesc* blk, const void* W,
+                           const float2* x, int64_t ld_in, float2* y, int64_t ld_out, int nrhs, const float* scale,
+                           int mtiles, int ntiles, int64_t total) {
+#define MBF_LAUNCH(KER, WT, KCV, PFV)                                                                    \
+  hipLaunchKernelGGL((KER<ADJ, KCV, PFV>), grid, dim3(256), 0, st, blk, reinterpret_cast<const WT*>(W), x, \
+                     ld_in, y, ld_out, nrhs, scale, mtiles, ntiles, total)
+  if (prec == MBF_C64) {
+    switch (v) {
+      case 0: MBF_LAUNCH(k_stage_f32, float2, 16, false); break;
+      case 1: MBF_LAUNCH(k_stage_f32, float2, 16, true); break;
+      case 2: MBF_LAUNCH(k_stage_f32, float2, 32, false); break;
+      default: MBF_LAUNCH(k_stage_f32, float2, 32, true); break;
+    }
+  } else {
+    switch (v) {
+      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, 16, false); break;
+      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, 16, true); break;
+      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, 32, false); break;
+      default: MBF_LAUNCH(k_stage_bf16x3, uint2, 32, true); break;
+    }
+  }
+#undef MBF_LAUNCH
+}
+
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const BlockDesc* blk, const void* W,
                         const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs, const float* scale,
-                        hipStream_t st) {
+                        hipStream_t st, int force_variant) {
   const int Rmax = adj ? P.max_K[s] : P.max_M[s];
+  const int Qmax = adj ? P.max_M[s] : P.max_K[s];
   const int mtiles = std::max(1, (Rmax + TM - 1) / TM);
   const int ntiles = (nrhs + TN - 1) / TN;
   const int64_t total = (int64_t)P.nblk[s] * mtiles * ntiles;
   const int64_t grid = (total + kXcd - 1) / kXcd * kXcd;
   if (grid > INT32_MAX) return {MBF_ERR_UNSUPPORTED, "stage grid too large"};
+  if (prec != MBF_C64 && prec != MBF_C64_SPLIT_BF16) return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel"};
+  const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, adj, Rmax, Qmax, nrhs);
   const float2* x = reinterpret_cast<const float2*>(in);
   float2* y = reinterpret_cast<float2*>(out);
-  if (prec == MBF_C64) {
-    const float2* w = reinterpret_cast<const float2*>(W);
-    if (adj)
-      hipLaunchKernelGGL(k_stage_f32<true>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y, ld_out,
-                         nrhs, scale, mtiles, ntiles, total);
-    else
-      hipLaunchKernelGGL(k_stage_f32<false>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y, ld_out,
-                         nrhs, scale, mtiles, ntiles, total);
-  } else if (prec == MBF_C64_SPLIT_BF16) {
-    const uint2* w = reinterpret_cast<const uint2*>(W);
-    if (adj)
-      hipLaunchKernelGGL(k_stage_bf16x3<true>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y,
-                         ld_out, nrhs, scale, mtiles, ntiles, total);
-    else
-      hipLaunchKernelGGL(k_stage_bf16x3<false>, dim3((unsigned)grid), dim3(256), 0, st, blk, w, x, ld_in, y,
-                         ld_out, nrhs, scale, mtiles, ntiles, total);
-  } else {
-    return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel for this precision"};
-  }
+  if (adj)
+    launch_variant<true>(prec, v, dim3((unsigned)grid), st, blk, W, x, ld_in, y, ld_out, nrhs, scale, mtiles, ntiles,
+                         total);
+  else
+    launch_variant<false>(prec, v, dim3((unsigned)grid), st, blk, W, x, ld_in, y, ld_out, nrhs, scale, mtiles, ntiles,
+                          total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return {MBF_ERR_HIP, std::string("stage launch: ") + hipGetErrorString(e)};
+  return {MBF_OK, ""};
+}
+
+}  // namespace mbf
+
+namespace mbf {
+
+Error autotune_stage(const DevPart& P, int s, int prec, bool adj, const BlockDesc* blk, const void* W,
+                     const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs, hipStream_t st,
+                     int* chosen, float* best_ms) {
+  const int Rmax = adj ? P.max_K[s] : P.max_M[s];
+  const int Qmax = adj ? P.max_M[s] : P.max_K[s];
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return {MBF_ERR_HIP, "hipEventCreate"};
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return {MBF_ERR_HIP, "hipEventCreate"};
+  }
+  int best = -1;
+  float bt = 0.f;
+  Error err{MBF_OK, ""};
+  for (int v = 0; v < kNumVariants && err.st == MBF_OK; ++v) {
+    err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, v);
+    if (err.st != MBF_OK) break;
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && err.st == MBF_OK; ++r)
+      err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, v);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      err = {MBF_ERR_HIP, "autotune timing"};
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best < 0 || ms < bt) {
+      best = v;
+      bt = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err.st != MBF_OK) return err;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_tune_file_locked();
+    const TuneKey k = tune_key(prec, adj, Rmax, Qmax, nrhs);
+    g_tune[k] = best;
+    if (const char* path = std::getenv("MBF_TUNE_FILE")) {
+      if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                     std::get<4>(k), best);
+        std::fclose(f);
+      }
+    }
+  }
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = bt / 2.f;
   return {MBF_OK, ""};
 }
 

@@ -220,3 +220,24 @@ def test_save_load_roundtrip_is_bit_exact(tmp_path):
     open(path, "wb").write(data[: len(data) // 2])
     with pytest.raises(_mbf().MBFError):
         _mbf().Factor.load(path)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", ["c64", "bf16x3"])
+def test_every_stage_kernel_variant_is_exact(variant, prec, monkeypatch):
+    """The autotuner may pick any variant: all of them must meet the bar."""
+    monkeypatch.setenv("MBF_STAGE_VARIANT", str(variant))
+    n = 32
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, [prec])
+    _check_both(F, bf, n * n, n * n, 100, prec, seed=variant)
+
+
+def test_autotune_keeps_results_within_bar():
+    n = 32
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, ["c64", "bf16x3"])
+    assert F.autotune("c64", 96) > 0
+    assert F.autotune("bf16x3", 96) > 0
+    _check_both(F, bf, n * n, n * n, 96, "c64", seed=5)
+    _check_both(F, bf, n * n, n * n, 96, "bf16x3", seed=6)
