@@ -54,9 +54,13 @@ __device__ __forceinline__ C czero() {
   return r;
 }
 
+// Selects instead of an indexed load keep the descriptor in registers.
 __device__ __forceinline__ int32_t group_row(const BlockDesc& d, int32_t i) {
-  const int t = (i >= d.ms[1]) + (i >= d.ms[2]) + (i >= d.ms[3]);
-  return d.orow[t] + i - d.ms[t];
+  int32_t base = d.orow[0] - d.ms[0];
+  base = i >= d.ms[1] ? d.orow[1] - d.ms[1] : base;
+  base = i >= d.ms[2] ? d.orow[2] - d.ms[2] : base;
+  base = i >= d.ms[3] ? d.orow[3] - d.ms[3] : base;
+  return base + i;
 }
 
 // ------------------------------------------------------------------ stage

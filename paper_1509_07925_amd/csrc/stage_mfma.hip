@@ -42,9 +42,14 @@ constexpr int TN = 64;   // right-hand sides per tile
 constexpr int TM = 64;   // complex output rows per tile
 constexpr int kXcd = 8;  // XCDs per device
 
+// Selects instead of an indexed load keep the descriptor in registers (a
+// run-time index into its arrays would place it in private memory).
 __device__ __forceinline__ int32_t grp_row(const BlockDesc& d, int32_t i) {
-  const int t = (i >= d.ms[1]) + (i >= d.ms[2]) + (i >= d.ms[3]);
-  return d.orow[t] + i - d.ms[t];
+  int32_t base = d.orow[0] - d.ms[0];
+  base = i >= d.ms[1] ? d.orow[1] - d.ms[1] : base;
+  base = i >= d.ms[2] ? d.orow[2] - d.ms[2] : base;
+  base = i >= d.ms[3] ? d.orow[3] - d.ms[3] : base;
+  return base + i;
 }
 
 __device__ __forceinline__ uint32_t f2bf_bits(float f) {
@@ -97,37 +102,44 @@ __device__ __forceinline__ Tile map_tile(int64_t total, int mtiles, int ntiles) 
   return r;
 }
 
-template <bool ADJ>
-__device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int n0, const v16f* acc, int nacc,
+// Store the wave's NS x 2 accumulator tiles (32 x 32 real each): rows are
+// right-hand sides wn + 32 ns + (MFMA row), columns real output columns
+// wm + 32 cs + (lane % 32); lanes of a row write consecutive floats.
+template <bool ADJ, int NS>
+__device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int n0, const v16f (&acc)[NS][2],
                                           int wn, int wm, float2* __restrict__ out, int64_t ld_out, int nrhs,
                                           const float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   float* o = reinterpret_cast<float*>(out);
-  for (int i = 0; i < nacc; ++i) {
-    const int col = wm + i * 32 + (lane & 31);  // real output column
+#pragma unroll
+  for (int cs = 0; cs < 2; ++cs) {
+    const int col = wm + cs * 32 + (lane & 31);  // real output column
     const int m = r0 + (col >> 1);
     if (m >= R) continue;
     const int32_t row = ADJ ? d.in_row + m : grp_row(d, m);
-    const float s = scale ? scale[row] : 1.0f;
+    const float sc = scale ? scale[row] : 1.0f;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int n = n0 + wn + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-      if (n < nrhs) o[2 * ((int64_t)n * ld_out + row) + (col & 1)] = acc[i][j] * s;
-    }
+    for (int ns = 0; ns < NS; ++ns)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int n = n0 + wn + 32 * ns + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        if (n < nrhs) o[2 * ((int64_t)n * ld_out + row) + (col & 1)] = acc[ns][cs][j] * sc;
+      }
   }
 }
 
 // ------------------------------------------------------------------ loads
-// Each chunk moves a TN x KC tile of the input state (A) and a KC x TM tile
-// of the block (B) into LDS, KC/4 entries per thread, with consecutive lanes
-// on consecutive memory (the reduction index for A and for the adjoint's
-// B, the output index for the forward B).  With PF the registers for the
-// next chunk are loaded while the matrix cores work on the current one.
-template <int KC, bool ADJ, typename WT>
+// Each chunk moves a TNV x KC tile of the input state (A) and a KC x TM tile
+// of the block (B) into LDS, with consecutive lanes on consecutive memory
+// (the reduction index for A and for the adjoint's B, the output index for
+// the forward B).  With PF the registers for the next chunk are loaded while
+// the matrix cores work on the current one.
+template <int TNV, int KC, bool ADJ, typename WT>
 struct Loader {
-  static constexpr int E = KC / 4;
-  float2 a[E];
-  WT b[E];
+  static constexpr int EA = TNV * KC / 256;
+  static constexpr int EB = TM * KC / 256;
+  float2 a[EA];
+  WT b[EB];
   __device__ __forceinline__ void load(const BlockDesc& d, const float2* __restrict__ in, int64_t ld_in,
                                        const WT* __restrict__ Wb, int R, int Q, int r0, int n0, int q0,
                                        int nrhs) {
@@ -138,7 +150,7 @@ struct Loader {
       int32_t row = 0;
       if (q < Q) row = ADJ ? grp_row(d, q) : d.in_row + q;
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
+      for (int j = 0; j < EA; ++j) {
         const int gn = n0 + n + j * (256 / KC);
         float2 v = make_float2(0.f, 0.f);
         if (gn < nrhs && q < Q) v = in[(int64_t)gn * ld_in + row];
@@ -148,7 +160,7 @@ struct Loader {
     if (!ADJ) {  // W(m, k), m contiguous: m = tid % 64, k = tid / 64 + 4 j
       const int m = r0 + (tid & 63), kb = tid >> 6;
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
+      for (int j = 0; j < EB; ++j) {
         const int q = q0 + kb + 4 * j;
         WT w{};
         if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
@@ -157,7 +169,7 @@ struct Loader {
     } else {  // W(m', k'), m' contiguous: m' = tid % KC, k' = tid / KC + j * (256 / KC)
       const int mr = q0 + tid % KC, kp = tid / KC;
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
+      for (int j = 0; j < EB; ++j) {
         const int kout = r0 + kp + j * (256 / KC);
         WT w{};
         if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
@@ -168,7 +180,9 @@ struct Loader {
 };
 
 // ------------------------------------------------------------------ FP32
-template <bool ADJ, int KC, bool PF>
+// Wave layout: 4 waves; wave w covers right-hand sides wn = (w % 2) * TNV / 2
+// (NS = TNV / 64 subtiles of 32) and real columns wm = (w / 2) * 64.
+template <bool ADJ, int TNV, int KC, bool PF>
 __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__ blk,
                                                    const float2* __restrict__ W,
                                                    const float2* __restrict__ in, int64_t ld_in,
@@ -176,7 +190,8 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
                                                    const float* __restrict__ scale, int mtiles, int ntiles,
                                                    int64_t total) {
   constexpr int P = KC + 4;
-  __shared__ __attribute__((aligned(16))) float As[2][TN][P];      // [re|im][n][k]
+  constexpr int NS = TNV / 64;
+  __shared__ __attribute__((aligned(16))) float As[2][TNV][P];     // [re|im][n][k]
   __shared__ __attribute__((aligned(16))) float Bs[2][2 * TM][P];  // [c][real col][k]
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
@@ -185,28 +200,28 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
   const int Q = ADJ ? d.M : d.K;
   const int r0 = tl.mt * TM;
   if (r0 >= R) return;
-  const int n0 = tl.nt * TN;
+  const int n0 = tl.nt * TNV;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * (TNV / 2), wm = (wave >> 1) * 64;
   const float2* Wb = W + d.w_off;
-  v16f acc[2], cmp[2];
-  acc[0] = acc[1] = cmp[0] = cmp[1] = v16f{};
-  Loader<KC, ADJ, float2> ld;
+  v16f acc[NS][2], cmp[NS][2];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) acc[a][0] = acc[a][1] = cmp[a][0] = cmp[a][1] = v16f{};
+  Loader<TNV, KC, ADJ, float2> ld;
   if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
     if (!PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
     {  // registers -> LDS
-      constexpr int E = KC / 4;
       const int k = tid % KC, n = tid / KC;
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
+      for (int j = 0; j < Loader<TNV, KC, ADJ, float2>::EA; ++j) {
         As[0][n + j * (256 / KC)][k] = ld.a[j].x;
         As[1][n + j * (256 / KC)][k] = ld.a[j].y;
       }
       if (!ADJ) {
         const int c = 2 * (tid & 63), kb = tid >> 6;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int j = 0; j < Loader<TNV, KC, ADJ, float2>::EB; ++j) {
           const float2 w = ld.b[j];
           const int kk = kb + 4 * j;
           Bs[0][c][kk] = w.x;
@@ -217,7 +232,7 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
       } else {
         const int mr = tid % KC, kp = tid / KC;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int j = 0; j < Loader<TNV, KC, ADJ, float2>::EB; ++j) {
           const float2 w = ld.b[j];
           const int c = 2 * (kp + j * (256 / KC));
           Bs[0][c][mr] = w.x;
@@ -230,34 +245,47 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
     __syncthreads();
     if (PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
     const int kk = lane >> 5, li = lane & 31;
-    v16f p0 = v16f{}, p1 = v16f{};
+    v16f p[NS][2];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) p[a][0] = p[a][1] = v16f{};
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 4) {
-      const float4 a = *reinterpret_cast<const float4*>(&As[kk][wn + li][kb]);
-      const float4 b0 = *reinterpret_cast<const float4*>(&Bs[kk][wm + li][kb]);
-      const float4 b1 = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 + li][kb]);
-      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0.x, p0, 0, 0, 0);
-      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b1.x, p1, 0, 0, 0);
-      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b0.y, p0, 0, 0, 0);
-      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1.y, p1, 0, 0, 0);
-      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b0.z, p0, 0, 0, 0);
-      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b1.z, p1, 0, 0, 0);
-      p0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b0.w, p0, 0, 0, 0);
-      p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b1.w, p1, 0, 0, 0);
+      float4 av[NS], bv[2];
+#pragma unroll
+      for (int a = 0; a < NS; ++a) av[a] = *reinterpret_cast<const float4*>(&As[kk][wn + 32 * a + li][kb]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bv[c] = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 * c + li][kb]);
+#pragma unroll
+      for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[c].x, p[a][c], 0, 0, 0);
+          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, bv[c].y, p[a][c], 0, 0, 0);
+          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].z, bv[c].z, p[a][c], 0, 0, 0);
+          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].w, bv[c].w, p[a][c], 0, 0, 0);
+        }
     }
-    fold(acc[0], cmp[0], p0);
-    fold(acc[1], cmp[1], p1);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      fold(acc[a][0], cmp[a][0], p[a][0]);
+      fold(acc[a][1], cmp[a][1], p[a][1]);
+    }
     __syncthreads();
   }
-  acc[0] += cmp[0];
-  acc[1] += cmp[1];
-  store_out<ADJ>(d, R, r0, n0, acc, 2, wn, wm, out, ld_out, nrhs, scale);
+#pragma unroll
+  for (int a = 0; a < NS; ++a) {
+    acc[a][0] += cmp[a][0];
+    acc[a][1] += cmp[a][1];
+  }
+  store_out<ADJ, NS>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
 // ------------------------------------------------------------------ BF16 x3
 // LDS rows hold interleaved pairs along the complex reduction index: entry
-// (row, k) is one 32-bit word = two BF16 values (real-k 2k and 2k+1).
-template <bool ADJ, int KC, bool PF>
+// (row, k) is one 32-bit word = two BF16 values (real-k 2k and 2k+1).  The
+// split products carry ~2^-16 relative error, so the partial sums go straight
+// into the matrix-core accumulators (no compensation).
+template <bool ADJ, int TNV, int KC, bool PF>
 __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restrict__ blk,
                                                       const uint2* __restrict__ W,  // (re_hi,im_hi | re_lo,im_lo)
                                                       const float2* __restrict__ in, int64_t ld_in,
@@ -265,7 +293,8 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
                                                       const float* __restrict__ scale, int mtiles, int ntiles,
                                                       int64_t total) {
   constexpr int P = KC + 4;  // words per LDS row (16-byte aligned rows)
-  __shared__ __attribute__((aligned(16))) uint32_t Ah[TN][P], Al[TN][P];
+  constexpr int NS = TNV / 64;
+  __shared__ __attribute__((aligned(16))) uint32_t Ah[TNV][P], Al[TNV][P];
   __shared__ __attribute__((aligned(16))) uint32_t Bh[2 * TM][P], Bl[2 * TM][P];
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
@@ -274,21 +303,21 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
   const int Q = ADJ ? d.M : d.K;
   const int r0 = tl.mt * TM;
   if (r0 >= R) return;
-  const int n0 = tl.nt * TN;
+  const int n0 = tl.nt * TNV;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wn = (wave & 1) * 32, wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * (TNV / 2), wm = (wave >> 1) * 64;
   const uint2* Wb = W + d.w_off;
-  v16f acc[2], cmp[2];
-  acc[0] = acc[1] = cmp[0] = cmp[1] = v16f{};
-  Loader<KC, ADJ, uint2> ld;
+  v16f acc[NS][2];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) acc[a][0] = acc[a][1] = v16f{};
+  Loader<TNV, KC, ADJ, uint2> ld;
   if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
     if (!PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
     {  // registers -> LDS (state split into BF16 hi/lo here)
-      constexpr int E = KC / 4;
       const int k = tid % KC, n = tid / KC;
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
+      for (int j = 0; j < Loader<TNV, KC, ADJ, uint2>::EA; ++j) {
         uint32_t rh, rl, ih, il;
         split_bf(ld.a[j].x, rh, rl);
         split_bf(ld.a[j].y, ih, il);
@@ -298,7 +327,7 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
       if (!ADJ) {
         const int c = 2 * (tid & 63), kb = tid >> 6;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int j = 0; j < Loader<TNV, KC, ADJ, uint2>::EB; ++j) {
           const uint2 w = ld.b[j];
           const int kk = kb + 4 * j;
           const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
@@ -311,7 +340,7 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
       } else {
         const int mr = tid % KC, kp = tid / KC;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int j = 0; j < Loader<TNV, KC, ADJ, uint2>::EB; ++j) {
           const uint2 w = ld.b[j];
           const int c = 2 * (kp + j * (256 / KC));
           const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
@@ -326,35 +355,37 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
     __syncthreads();
     if (PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
     const int kh = lane >> 5, li = lane & 31;
-    v16f part[2] = {v16f{}, v16f{}};
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 8) {
       // lane holds real-k 8*kh .. 8*kh+7 of this step = complex k kb + 4*kh .. +3
       const int ko = kb + 4 * kh;
-      const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[wn + li][ko]));
-      const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[wn + li][ko]));
+      bf16x8 ah[NS], al[NS], bh[2], bl[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[wm + 32 * i + li][ko]));
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[wm + 32 * i + li][ko]));
-        part[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, part[i], 0, 0, 0);
-        part[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, part[i], 0, 0, 0);
-        part[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, part[i], 0, 0, 0);
+      for (int a = 0; a < NS; ++a) {
+        ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[wn + 32 * a + li][ko]));
+        al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[wn + 32 * a + li][ko]));
       }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[wm + 32 * c + li][ko]));
+        bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[wm + 32 * c + li][ko]));
+      }
+#pragma unroll
+      for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
+          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
+          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
+        }
     }
-    fold(acc[0], cmp[0], part[0]);
-    fold(acc[1], cmp[1], part[1]);
     __syncthreads();
   }
-  acc[0] += cmp[0];
-  acc[1] += cmp[1];
-  store_out<ADJ>(d, R, r0, n0, acc, 2, wn, wm, out, ld_out, nrhs, scale);
+  store_out<ADJ, NS>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
 }  // namespace
 
-// FP32: the matrix cores pay off once a block's vectors are reused across
-// enough right-hand sides; below that the generic kernel streams the block.
 bool use_mfma(const DevPart&, int, int64_t nrhs, int prec) {
   if (prec == MBF_C64_SPLIT_BF16) return true;
   if (prec == MBF_C64) return nrhs >= 32;
@@ -402,28 +433,35 @@ int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
   return prec == MBF_C64 ? 0 : 3;
 }
 
-// Kernel variants: (reduction chunk, register prefetch).  variant index:
-//   0 = (16, off)  1 = (16, on)  2 = (32, off)  3 = (32, on)
+// Kernel variants (RHS tile, reduction chunk, register prefetch):
+//   0 = (64, 16, off)  1 = (64, 16, on)  2 = (64, 32, off)  3 = (64, 32, on)
+//   4 = (128, 16, on)  5 = (128, 32, on)
+static int variant_tn(int v) { return v >= 4 ? 128 : 64; }
+
 template <bool ADJ>
 static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const BlockDesc* blk, const void* W,
                            const float2* x, int64_t ld_in, float2* y, int64_t ld_out, int nrhs, const float* scale,
                            int mtiles, int ntiles, int64_t total) {
-#define MBF_LAUNCH(KER, WT, KCV, PFV)                                                                    \
-  hipLaunchKernelGGL((KER<ADJ, KCV, PFV>), grid, dim3(256), 0, st, blk, reinterpret_cast<const WT*>(W), x, \
+#define MBF_LAUNCH(KER, WT, TNV, KCV, PFV)                                                                    \
+  hipLaunchKernelGGL((KER<ADJ, TNV, KCV, PFV>), grid, dim3(256), 0, st, blk, reinterpret_cast<const WT*>(W), x, \
                      ld_in, y, ld_out, nrhs, scale, mtiles, ntiles, total)
   if (prec == MBF_C64) {
     switch (v) {
-      case 0: MBF_LAUNCH(k_stage_f32, float2, 16, false); break;
-      case 1: MBF_LAUNCH(k_stage_f32, float2, 16, true); break;
-      case 2: MBF_LAUNCH(k_stage_f32, float2, 32, false); break;
-      default: MBF_LAUNCH(k_stage_f32, float2, 32, true); break;
+      case 0: MBF_LAUNCH(k_stage_f32, float2, 64, 16, false); break;
+      case 1: MBF_LAUNCH(k_stage_f32, float2, 64, 16, true); break;
+      case 2: MBF_LAUNCH(k_stage_f32, float2, 64, 32, false); break;
+      case 3: MBF_LAUNCH(k_stage_f32, float2, 64, 32, true); break;
+      case 4: MBF_LAUNCH(k_stage_f32, float2, 128, 16, true); break;
+      default: MBF_LAUNCH(k_stage_f32, float2, 128, 32, true); break;
     }
   } else {
     switch (v) {
-      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, 16, false); break;
-      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, 16, true); break;
-      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, 32, false); break;
-      default: MBF_LAUNCH(k_stage_bf16x3, uint2, 32, true); break;
+      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 16, false); break;
+      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 16, true); break;
+      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 32, false); break;
+      case 3: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 32, true); break;
+      case 4: MBF_LAUNCH(k_stage_bf16x3, uint2, 128, 16, true); break;
+      default: MBF_LAUNCH(k_stage_bf16x3, uint2, 128, 32, true); break;
     }
   }
 #undef MBF_LAUNCH
@@ -434,13 +472,14 @@ Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const Block
                         hipStream_t st, int force_variant) {
   const int Rmax = adj ? P.max_K[s] : P.max_M[s];
   const int Qmax = adj ? P.max_M[s] : P.max_K[s];
+  if (prec != MBF_C64 && prec != MBF_C64_SPLIT_BF16) return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel"};
+  const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, adj, Rmax, Qmax, nrhs);
+  const int tn = variant_tn(v);
   const int mtiles = std::max(1, (Rmax + TM - 1) / TM);
-  const int ntiles = (nrhs + TN - 1) / TN;
+  const int ntiles = (nrhs + tn - 1) / tn;
   const int64_t total = (int64_t)P.nblk[s] * mtiles * ntiles;
   const int64_t grid = (total + kXcd - 1) / kXcd * kXcd;
   if (grid > INT32_MAX) return {MBF_ERR_UNSUPPORTED, "stage grid too large"};
-  if (prec != MBF_C64 && prec != MBF_C64_SPLIT_BF16) return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel"};
-  const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, adj, Rmax, Qmax, nrhs);
   const float2* x = reinterpret_cast<const float2*>(in);
   float2* y = reinterpret_cast<float2*>(out);
   if (adj)

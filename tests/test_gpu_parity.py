@@ -222,15 +222,17 @@ def test_save_load_roundtrip_is_bit_exact(tmp_path):
         _mbf().Factor.load(path)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", list(range(6)))
 @pytest.mark.parametrize("prec", ["c64", "bf16x3"])
 def test_every_stage_kernel_variant_is_exact(variant, prec, monkeypatch):
-    """The autotuner may pick any variant: all of them must meet the bar."""
+    """The autotuner may pick any variant: all of them must meet the bar.
+    300 right-hand sides span several RHS tiles of either width (64, 128)
+    and end in a ragged one."""
     monkeypatch.setenv("MBF_STAGE_VARIANT", str(variant))
     n = 32
     bf = _dft_oracle(n, 2, 1e-6)
     F = _import(bf, [prec])
-    _check_both(F, bf, n * n, n * n, 100, prec, seed=variant)
+    _check_both(F, bf, n * n, n * n, 300, prec, seed=variant)
 
 
 def test_autotune_keeps_results_within_bar():
