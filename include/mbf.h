@@ -111,7 +111,8 @@ int mbf_kernel_fio(void* user, int64_t m, const int64_t* rows, int64_t k, const 
  *   oversample random-sampling oversampling (extra rows / columns).
  *   seed       seed of the random sampling.
  *   prec_mask  bit (1 << mbf_prec) for every precision to keep on device.
- *   threads    host threads for the build (0 = hardware concurrency).      */
+ *   threads    host threads for the build (0 = OMP_NUM_THREADS when set,
+ *              else the CPUs in the process's affinity mask).             */
 typedef struct {
   double tol;
   int32_t max_rank;

@@ -22,6 +22,8 @@
 #include <mutex>
 #include <random>
 #include <thread>
+#include <sched.h>
+#include <cstdlib>
 
 #include "linalg.h"
 
@@ -268,6 +270,22 @@ bool validate_opts(const mbf_opts& o, std::string& why) {
   return true;
 }
 
+// Build threads when the caller leaves the count open: OMP_NUM_THREADS when
+// set (the usual cap on shared machines), else the CPUs this process may run
+// on, else the hardware concurrency.
+static int default_threads() {
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+    const int c = CPU_COUNT(&set);
+    if (c > 0) return c;
+  }
+  return (int)std::max(1u, std::thread::hardware_concurrency());
+}
+
 HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
                       const std::vector<int64_t>& os, mbf_entry_cb cb, void* user, const mbf_opts& o) {
   HostFactor f;
@@ -278,7 +296,7 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   f.xt = xt;
   f.ot = ot;
   Ctx c{cb, user, &xs, &os};
-  const int threads = o.threads > 0 ? o.threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  const int threads = o.threads > 0 ? o.threads : default_threads();
   f.rank.resize(L + 1);
   for (int s = 0; s <= L; ++s) f.rank[s].assign((size_t)xt.nn(s) * ot.nn(L - s), -1);
   // per-block outputs, filled by the owning task
