@@ -12,9 +12,10 @@
 // so that D(n, 2m+d) is the real (d=0) / imaginary (d=1) part of out(n, m):
 // output rows are interleaved complex and store coalesced into the state.
 //
-// Tile: 64 right-hand sides x 64 complex output rows per workgroup (4 waves
-// of 32 x 64 real columns), reduction staged through LDS in chunks of 16
-// complex entries.  Two arithmetic modes:
+// Tile: 64 or 128 right-hand sides x 64 complex output rows per workgroup
+// (4 waves, each 32 or 64 right-hand sides x 64 real columns), reduction
+// staged through LDS in chunks of 16 or 32 complex entries; the chunk sums
+// are added to the running sums (two-level summation).  Two arithmetic modes:
 //   F32    v_mfma_f32_32x32x2_f32, one complex k per instruction;
 //   BF16X3 v_mfma_f32_32x32x16_bf16, eight complex k per instruction; every
 //          operand is split as hi + lo (both BF16) and the product is
@@ -62,26 +63,6 @@ __device__ __forceinline__ float bf_bits2f(uint32_t h) { return __uint_as_float(
 __device__ __forceinline__ void split_bf(float x, uint32_t& hi, uint32_t& lo) {
   hi = f2bf_bits(x);
   lo = f2bf_bits(x - bf_bits2f(hi));
-}
-
-// Error-free addition (Knuth TwoSum): s + e == a + b exactly.
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  const float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-// Fold one reduction chunk's partial sums into the running sums with a
-// compensation term (the matrix cores accumulate within a chunk only), so
-// the rounding error does not grow with the number of chunks.
-__device__ __forceinline__ void fold(v16f& sum, v16f& comp, const v16f& part) {
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    float s, e;
-    two_sum(sum[j], part[j], s, e);
-    sum[j] = s;
-    comp[j] += e;
-  }
 }
 
 struct Tile {
@@ -204,9 +185,12 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wn = (wave & 1) * (TNV / 2), wm = (wave >> 1) * 64;
   const float2* Wb = W + d.w_off;
-  v16f acc[NS][2], cmp[NS][2];
+  // Two-level summation: the matrix cores sum one chunk into p, which is then
+  // added to the running sums; the rounding error grows with the chunk
+  // length plus the number of chunks instead of with the full reduction.
+  v16f acc[NS][2];
 #pragma unroll
-  for (int a = 0; a < NS; ++a) acc[a][0] = acc[a][1] = cmp[a][0] = cmp[a][1] = v16f{};
+  for (int a = 0; a < NS; ++a) acc[a][0] = acc[a][1] = v16f{};
   Loader<TNV, KC, ADJ, float2> ld;
   if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
@@ -267,15 +251,10 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
     }
 #pragma unroll
     for (int a = 0; a < NS; ++a) {
-      fold(acc[a][0], cmp[a][0], p[a][0]);
-      fold(acc[a][1], cmp[a][1], p[a][1]);
+      acc[a][0] += p[a][0];
+      acc[a][1] += p[a][1];
     }
     __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < NS; ++a) {
-    acc[a][0] += cmp[a][0];
-    acc[a][1] += cmp[a][1];
   }
   store_out<ADJ, NS>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
