@@ -12,9 +12,8 @@ namespace mbf {
 // the split layout).
 bool use_mfma(const DevPart& P, int s, int64_t nrhs, int prec);
 
-// Stage kernel variants (RHS tile 64 / 128, reduction chunk 16 / 32,
-// register prefetch off / on).
-constexpr int kNumVariants = 6;
+// Stage kernel variants (tile shape, reduction chunk, register prefetch).
+constexpr int kNumVariants = 8;
 
 // force_variant >= 0 bypasses the tuned choice.
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adjoint, const BlockDesc* blk,

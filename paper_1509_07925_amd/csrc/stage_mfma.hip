@@ -39,9 +39,8 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int TN = 64;   // right-hand sides per tile
-constexpr int TM = 64;   // complex output rows per tile
-constexpr int kXcd = 8;  // XCDs per device
+constexpr int kTuneRhs = 64;  // right-hand-side bucket of the tuning key
+constexpr int kXcd = 8;       // XCDs per device
 
 // Selects instead of an indexed load keep the descriptor in registers (a
 // run-time index into its arrays would place it in private memory).
@@ -83,75 +82,95 @@ __device__ __forceinline__ Tile map_tile(int64_t total, int mtiles, int ntiles) 
   return r;
 }
 
-// Store the wave's NS x 2 accumulator tiles (32 x 32 real each): rows are
-// right-hand sides wn + 32 ns + (MFMA row), columns real output columns
-// wm + 32 cs + (lane % 32); lanes of a row write consecutive floats.
-template <bool ADJ, int NS>
-__device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int n0, const v16f (&acc)[NS][2],
+// Tile shape of a kernel variant: TNV right-hand sides x TMV complex output
+// rows per workgroup of NTH threads; each wave owns RT x CT matrix-core tiles
+// of 32 right-hand sides x 32 real columns; the reduction runs in chunks of
+// KC complex entries, with register prefetch of the next chunk when PF.
+template <int TNV_, int TMV_, int NTH_, int RT_, int CT_, int KC_, bool PF_>
+struct Shape {
+  static constexpr int TNV = TNV_, TMV = TMV_, NTH = NTH_, RT = RT_, CT = CT_, KC = KC_;
+  static constexpr bool PF = PF_;
+  static constexpr int WR = TNV / (32 * RT);      // waves along right-hand sides
+  static constexpr int WC = 2 * TMV / (32 * CT);  // waves along real columns
+  static_assert(WR * WC * 64 == NTH, "the waves must cover the tile");
+  static constexpr int EA = TNV * KC / NTH;  // state entries per thread per chunk
+  static constexpr int EB = TMV * KC / NTH;  // block entries per thread per chunk
+  static_assert(EA * NTH == TNV * KC && EB * NTH == TMV * KC, "load mapping");
+  static_assert(NTH % KC == 0 && NTH % TMV == 0 && KC % (NTH / TMV) == 0, "load mapping");
+  static constexpr int P = KC + 4;  // LDS row pitch in words (16-byte aligned rows)
+};
+
+// Store the wave's RT x CT accumulator tiles (32 x 32 real each): rows are
+// right-hand sides wn + 32 a + (MFMA row), columns real output columns
+// wm + 32 c + (lane % 32); lanes of a row write consecutive floats.
+template <bool ADJ, int RT, int CT>
+__device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int n0, const v16f (&acc)[RT][CT],
                                           int wn, int wm, float2* __restrict__ out, int64_t ld_out, int nrhs,
                                           const float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   float* o = reinterpret_cast<float*>(out);
 #pragma unroll
-  for (int cs = 0; cs < 2; ++cs) {
-    const int col = wm + cs * 32 + (lane & 31);  // real output column
+  for (int c = 0; c < CT; ++c) {
+    const int col = wm + c * 32 + (lane & 31);  // real output column
     const int m = r0 + (col >> 1);
     if (m >= R) continue;
     const int32_t row = ADJ ? d.in_row + m : grp_row(d, m);
     const float sc = scale ? scale[row] : 1.0f;
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns)
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int n = n0 + wn + 32 * ns + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-        if (n < nrhs) o[2 * ((int64_t)n * ld_out + row) + (col & 1)] = acc[ns][cs][j] * sc;
+        const int n = n0 + wn + 32 * a + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        if (n < nrhs) o[2 * ((int64_t)n * ld_out + row) + (col & 1)] = acc[a][c][j] * sc;
       }
   }
 }
 
 // ------------------------------------------------------------------ loads
-// Each chunk moves a TNV x KC tile of the input state (A) and a KC x TM tile
-// of the block (B) into LDS, with consecutive lanes on consecutive memory
-// (the reduction index for A and for the adjoint's B, the output index for
-// the forward B).  With PF the registers for the next chunk are loaded while
-// the matrix cores work on the current one.
-template <int TNV, int KC, bool ADJ, typename WT>
+// Each chunk moves a TNV x KC tile of the input state (A) and a KC x TMV
+// tile of the block (B) into registers, with consecutive lanes on
+// consecutive memory (the reduction index for A and for the adjoint's B, the
+// output index for the forward B).  With PF the registers for the next chunk
+// are loaded while the matrix cores work on the current one.
+//   A:             k = tid % KC,  n = tid / KC + j (NTH / KC)
+//   B (forward):   m = tid % TMV, k = tid / TMV + j (NTH / TMV)
+//   B (adjoint):   m' = tid % KC, k' = tid / KC + j (NTH / KC)
+template <class S, bool ADJ, typename WT>
 struct Loader {
-  static constexpr int EA = TNV * KC / 256;
-  static constexpr int EB = TM * KC / 256;
-  float2 a[EA];
-  WT b[EB];
+  float2 a[S::EA];
+  WT b[S::EB];
   __device__ __forceinline__ void load(const BlockDesc& d, const float2* __restrict__ in, int64_t ld_in,
                                        const WT* __restrict__ Wb, int R, int Q, int r0, int n0, int q0,
                                        int nrhs) {
+    constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV;
     const int tid = threadIdx.x;
-    {  // A(n, k): k = tid % KC, rows tid / KC + j * (256 / KC)
+    {
       const int k = tid % KC, n = tid / KC;
       const int q = q0 + k;
       int32_t row = 0;
       if (q < Q) row = ADJ ? grp_row(d, q) : d.in_row + q;
 #pragma unroll
-      for (int j = 0; j < EA; ++j) {
-        const int gn = n0 + n + j * (256 / KC);
+      for (int j = 0; j < S::EA; ++j) {
+        const int gn = n0 + n + j * (NTH / KC);
         float2 v = make_float2(0.f, 0.f);
         if (gn < nrhs && q < Q) v = in[(int64_t)gn * ld_in + row];
         a[j] = v;
       }
     }
-    if (!ADJ) {  // W(m, k), m contiguous: m = tid % 64, k = tid / 64 + 4 j
-      const int m = r0 + (tid & 63), kb = tid >> 6;
+    if (!ADJ) {
+      const int m = r0 + tid % TMV, kb = tid / TMV;
 #pragma unroll
-      for (int j = 0; j < EB; ++j) {
-        const int q = q0 + kb + 4 * j;
+      for (int j = 0; j < S::EB; ++j) {
+        const int q = q0 + kb + j * (NTH / TMV);
         WT w{};
         if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
         b[j] = w;
       }
-    } else {  // W(m', k'), m' contiguous: m' = tid % KC, k' = tid / KC + j * (256 / KC)
+    } else {
       const int mr = q0 + tid % KC, kp = tid / KC;
 #pragma unroll
-      for (int j = 0; j < EB; ++j) {
-        const int kout = r0 + kp + j * (256 / KC);
+      for (int j = 0; j < S::EB; ++j) {
+        const int kout = r0 + kp + j * (NTH / KC);
         WT w{};
         if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
         b[j] = w;
@@ -161,53 +180,54 @@ struct Loader {
 };
 
 // ------------------------------------------------------------------ FP32
-// Wave layout: 4 waves; wave w covers right-hand sides wn = (w % 2) * TNV / 2
-// (NS = TNV / 64 subtiles of 32) and real columns wm = (w / 2) * 64.
-template <bool ADJ, int TNV, int KC, bool PF>
-__global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__ blk,
-                                                   const float2* __restrict__ W,
-                                                   const float2* __restrict__ in, int64_t ld_in,
-                                                   float2* __restrict__ out, int64_t ld_out, int nrhs,
-                                                   const float* __restrict__ scale, int mtiles, int ntiles,
-                                                   int64_t total) {
-  constexpr int P = KC + 4;
-  constexpr int NS = TNV / 64;
-  __shared__ __attribute__((aligned(16))) float As[2][TNV][P];     // [re|im][n][k]
-  __shared__ __attribute__((aligned(16))) float Bs[2][2 * TM][P];  // [c][real col][k]
+// Wave w covers right-hand sides wn = (w % WR) * 32 RT and real columns
+// wm = (w / WR) * 32 CT.
+template <bool ADJ, class S>
+__global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restrict__ blk,
+                                                      const float2* __restrict__ W,
+                                                      const float2* __restrict__ in, int64_t ld_in,
+                                                      float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                      const float* __restrict__ scale, int mtiles, int ntiles,
+                                                      int64_t total) {
+  constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV, P = S::P, RT = S::RT, CT = S::CT;
+  __shared__ __attribute__((aligned(16))) float As[2][S::TNV][P];  // [re|im][n][k]
+  __shared__ __attribute__((aligned(16))) float Bs[2][2 * TMV][P];  // [c][real col][k]
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
   const BlockDesc d = blk[tl.b];
   const int R = ADJ ? d.K : d.M;
   const int Q = ADJ ? d.M : d.K;
-  const int r0 = tl.mt * TM;
+  const int r0 = tl.mt * TMV;
   if (r0 >= R) return;
-  const int n0 = tl.nt * TNV;
+  const int n0 = tl.nt * S::TNV;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wn = (wave & 1) * (TNV / 2), wm = (wave >> 1) * 64;
+  const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
   const float2* Wb = W + d.w_off;
   // Two-level summation: the matrix cores sum one chunk into p, which is then
   // added to the running sums; the rounding error grows with the chunk
   // length plus the number of chunks instead of with the full reduction.
-  v16f acc[NS][2];
+  v16f acc[RT][CT];
 #pragma unroll
-  for (int a = 0; a < NS; ++a) acc[a][0] = acc[a][1] = v16f{};
-  Loader<TNV, KC, ADJ, float2> ld;
-  if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
+  Loader<S, ADJ, float2> ld;
+  if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
-    if (!PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+    if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
     {  // registers -> LDS
       const int k = tid % KC, n = tid / KC;
 #pragma unroll
-      for (int j = 0; j < Loader<TNV, KC, ADJ, float2>::EA; ++j) {
-        As[0][n + j * (256 / KC)][k] = ld.a[j].x;
-        As[1][n + j * (256 / KC)][k] = ld.a[j].y;
+      for (int j = 0; j < S::EA; ++j) {
+        As[0][n + j * (NTH / KC)][k] = ld.a[j].x;
+        As[1][n + j * (NTH / KC)][k] = ld.a[j].y;
       }
       if (!ADJ) {
-        const int c = 2 * (tid & 63), kb = tid >> 6;
+        const int c = 2 * (tid % TMV), kb = tid / TMV;
 #pragma unroll
-        for (int j = 0; j < Loader<TNV, KC, ADJ, float2>::EB; ++j) {
+        for (int j = 0; j < S::EB; ++j) {
           const float2 w = ld.b[j];
-          const int kk = kb + 4 * j;
+          const int kk = kb + j * (NTH / TMV);
           Bs[0][c][kk] = w.x;
           Bs[0][c + 1][kk] = w.y;
           Bs[1][c][kk] = -w.y;
@@ -216,9 +236,9 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
       } else {
         const int mr = tid % KC, kp = tid / KC;
 #pragma unroll
-        for (int j = 0; j < Loader<TNV, KC, ADJ, float2>::EB; ++j) {
+        for (int j = 0; j < S::EB; ++j) {
           const float2 w = ld.b[j];
-          const int c = 2 * (kp + j * (256 / KC));
+          const int c = 2 * (kp + j * (NTH / KC));
           Bs[0][c][mr] = w.x;
           Bs[0][c + 1][mr] = -w.y;
           Bs[1][c][mr] = w.y;
@@ -227,22 +247,24 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
       }
     }
     __syncthreads();
-    if (PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
+    if (S::PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
     const int kk = lane >> 5, li = lane & 31;
-    v16f p[NS][2];
+    v16f p[RT][CT];
 #pragma unroll
-    for (int a = 0; a < NS; ++a) p[a][0] = p[a][1] = v16f{};
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) p[a][c] = v16f{};
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 4) {
-      float4 av[NS], bv[2];
+      float4 av[RT], bv[CT];
 #pragma unroll
-      for (int a = 0; a < NS; ++a) av[a] = *reinterpret_cast<const float4*>(&As[kk][wn + 32 * a + li][kb]);
+      for (int a = 0; a < RT; ++a) av[a] = *reinterpret_cast<const float4*>(&As[kk][wn + 32 * a + li][kb]);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) bv[c] = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 * c + li][kb]);
+      for (int c = 0; c < CT; ++c) bv[c] = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 * c + li][kb]);
 #pragma unroll
-      for (int a = 0; a < NS; ++a)
+      for (int a = 0; a < RT; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < CT; ++c) {
           p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[c].x, p[a][c], 0, 0, 0);
           p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, bv[c].y, p[a][c], 0, 0, 0);
           p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].z, bv[c].z, p[a][c], 0, 0, 0);
@@ -250,13 +272,12 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
         }
     }
 #pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      acc[a][0] += p[a][0];
-      acc[a][1] += p[a][1];
-    }
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[a][c] += p[a][c];
     __syncthreads();
   }
-  store_out<ADJ, NS>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+  store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
 // ------------------------------------------------------------------ BF16 x3
@@ -264,51 +285,52 @@ __global__ __launch_bounds__(256) void k_stage_f32(const BlockDesc* __restrict__
 // (row, k) is one 32-bit word = two BF16 values (real-k 2k and 2k+1).  The
 // split products carry ~2^-16 relative error, so the partial sums go straight
 // into the matrix-core accumulators (no compensation).
-template <bool ADJ, int TNV, int KC, bool PF>
-__global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restrict__ blk,
-                                                      const uint2* __restrict__ W,  // (re_hi,im_hi | re_lo,im_lo)
-                                                      const float2* __restrict__ in, int64_t ld_in,
-                                                      float2* __restrict__ out, int64_t ld_out, int nrhs,
-                                                      const float* __restrict__ scale, int mtiles, int ntiles,
-                                                      int64_t total) {
-  constexpr int P = KC + 4;  // words per LDS row (16-byte aligned rows)
-  constexpr int NS = TNV / 64;
-  __shared__ __attribute__((aligned(16))) uint32_t Ah[TNV][P], Al[TNV][P];
-  __shared__ __attribute__((aligned(16))) uint32_t Bh[2 * TM][P], Bl[2 * TM][P];
+template <bool ADJ, class S>
+__global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __restrict__ blk,
+                                                         const uint2* __restrict__ W,  // (re_hi,im_hi | re_lo,im_lo)
+                                                         const float2* __restrict__ in, int64_t ld_in,
+                                                         float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                         const float* __restrict__ scale, int mtiles, int ntiles,
+                                                         int64_t total) {
+  constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV, P = S::P, RT = S::RT, CT = S::CT;
+  __shared__ __attribute__((aligned(16))) uint32_t Ah[S::TNV][P], Al[S::TNV][P];
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[2 * TMV][P], Bl[2 * TMV][P];
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
   const BlockDesc d = blk[tl.b];
   const int R = ADJ ? d.K : d.M;
   const int Q = ADJ ? d.M : d.K;
-  const int r0 = tl.mt * TM;
+  const int r0 = tl.mt * TMV;
   if (r0 >= R) return;
-  const int n0 = tl.nt * TNV;
+  const int n0 = tl.nt * S::TNV;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wn = (wave & 1) * (TNV / 2), wm = (wave >> 1) * 64;
+  const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
   const uint2* Wb = W + d.w_off;
-  v16f acc[NS][2];
+  v16f acc[RT][CT];
 #pragma unroll
-  for (int a = 0; a < NS; ++a) acc[a][0] = acc[a][1] = v16f{};
-  Loader<TNV, KC, ADJ, uint2> ld;
-  if (PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
+  Loader<S, ADJ, uint2> ld;
+  if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
   for (int q0 = 0; q0 < Q; q0 += KC) {
-    if (!PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+    if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
     {  // registers -> LDS (state split into BF16 hi/lo here)
       const int k = tid % KC, n = tid / KC;
 #pragma unroll
-      for (int j = 0; j < Loader<TNV, KC, ADJ, uint2>::EA; ++j) {
+      for (int j = 0; j < S::EA; ++j) {
         uint32_t rh, rl, ih, il;
         split_bf(ld.a[j].x, rh, rl);
         split_bf(ld.a[j].y, ih, il);
-        Ah[n + j * (256 / KC)][k] = rh | (ih << 16);
-        Al[n + j * (256 / KC)][k] = rl | (il << 16);
+        Ah[n + j * (NTH / KC)][k] = rh | (ih << 16);
+        Al[n + j * (NTH / KC)][k] = rl | (il << 16);
       }
       if (!ADJ) {
-        const int c = 2 * (tid & 63), kb = tid >> 6;
+        const int c = 2 * (tid % TMV), kb = tid / TMV;
 #pragma unroll
-        for (int j = 0; j < Loader<TNV, KC, ADJ, uint2>::EB; ++j) {
+        for (int j = 0; j < S::EB; ++j) {
           const uint2 w = ld.b[j];
-          const int kk = kb + 4 * j;
+          const int kk = kb + j * (NTH / TMV);
           const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
           // column 2m (real part): (Wr, -Wi);  column 2m+1 (imag part): (Wi, Wr)
           Bh[c][kk] = reh | ((imh ^ 0x8000u) << 16);
@@ -319,9 +341,9 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
       } else {
         const int mr = tid % KC, kp = tid / KC;
 #pragma unroll
-        for (int j = 0; j < Loader<TNV, KC, ADJ, uint2>::EB; ++j) {
+        for (int j = 0; j < S::EB; ++j) {
           const uint2 w = ld.b[j];
-          const int c = 2 * (kp + j * (256 / KC));
+          const int c = 2 * (kp + j * (NTH / KC));
           const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
           // conj(W): column 2k' (real part): (Wr, Wi);  column 2k'+1 (imag part): (-Wi, Wr)
           Bh[c][mr] = reh | (imh << 16);
@@ -332,27 +354,27 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
       }
     }
     __syncthreads();
-    if (PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
+    if (S::PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
     const int kh = lane >> 5, li = lane & 31;
 #pragma unroll
     for (int kb = 0; kb < KC; kb += 8) {
       // lane holds real-k 8*kh .. 8*kh+7 of this step = complex k kb + 4*kh .. +3
       const int ko = kb + 4 * kh;
-      bf16x8 ah[NS], al[NS], bh[2], bl[2];
+      bf16x8 ah[RT], al[RT], bh[CT], bl[CT];
 #pragma unroll
-      for (int a = 0; a < NS; ++a) {
+      for (int a = 0; a < RT; ++a) {
         ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[wn + 32 * a + li][ko]));
         al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[wn + 32 * a + li][ko]));
       }
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < CT; ++c) {
         bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[wm + 32 * c + li][ko]));
         bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[wm + 32 * c + li][ko]));
       }
 #pragma unroll
-      for (int a = 0; a < NS; ++a)
+      for (int a = 0; a < RT; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < CT; ++c) {
           acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
           acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
           acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
@@ -360,7 +382,42 @@ __global__ __launch_bounds__(256) void k_stage_bf16x3(const BlockDesc* __restric
     }
     __syncthreads();
   }
-  store_out<ADJ, NS>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+  store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+}
+
+// Kernel variants: Shape<TNV, TMV, NTH, RT, CT, KC, PF>.
+using V0 = Shape<64, 64, 256, 1, 2, 16, false>;
+using V1 = Shape<64, 64, 256, 1, 2, 16, true>;
+using V2 = Shape<64, 64, 256, 1, 2, 32, false>;
+using V3 = Shape<64, 64, 256, 1, 2, 32, true>;
+using V4 = Shape<128, 64, 256, 2, 2, 16, true>;
+using V5 = Shape<128, 64, 256, 2, 2, 32, true>;
+// FP32 with 8 waves (two accumulator sets per tile bound the wave tile).
+using F6 = Shape<256, 64, 512, 2, 2, 16, true>;
+using F7 = Shape<128, 128, 512, 2, 2, 16, true>;
+// BF16 x3 with wide wave tiles (one accumulator set per tile).
+using B6 = Shape<256, 128, 512, 2, 4, 16, true>;
+using B7 = Shape<128, 128, 256, 2, 4, 16, true>;
+
+struct VariantDims {
+  int tnv, tmv, nth;
+};
+template <class S>
+constexpr VariantDims dims_of() {
+  return {S::TNV, S::TMV, S::NTH};
+}
+
+VariantDims variant_dims(int prec, int v) {
+  switch (v) {
+    case 0: return dims_of<V0>();
+    case 1: return dims_of<V1>();
+    case 2: return dims_of<V2>();
+    case 3: return dims_of<V3>();
+    case 4: return dims_of<V4>();
+    case 5: return dims_of<V5>();
+    case 6: return prec == MBF_C64 ? dims_of<F6>() : dims_of<B6>();
+    default: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B7>();
+  }
 }
 
 }  // namespace
@@ -383,7 +440,7 @@ std::map<TuneKey, int> g_tune;
 bool g_tune_loaded = false;
 
 TuneKey tune_key(int prec, bool adj, int R, int Q, int nrhs) {
-  return TuneKey{prec, adj ? 1 : 0, (R + 63) / 64, (Q + 63) / 64, (nrhs + TN - 1) / TN};
+  return TuneKey{prec, adj ? 1 : 0, (R + 63) / 64, (Q + 63) / 64, (nrhs + kTuneRhs - 1) / kTuneRhs};
 }
 
 void load_tune_file_locked() {
@@ -412,35 +469,34 @@ int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
   return prec == MBF_C64 ? 0 : 3;
 }
 
-// Kernel variants (RHS tile, reduction chunk, register prefetch):
-//   0 = (64, 16, off)  1 = (64, 16, on)  2 = (64, 32, off)  3 = (64, 32, on)
-//   4 = (128, 16, on)  5 = (128, 32, on)
-static int variant_tn(int v) { return v >= 4 ? 128 : 64; }
-
 template <bool ADJ>
 static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const BlockDesc* blk, const void* W,
                            const float2* x, int64_t ld_in, float2* y, int64_t ld_out, int nrhs, const float* scale,
                            int mtiles, int ntiles, int64_t total) {
-#define MBF_LAUNCH(KER, WT, TNV, KCV, PFV)                                                                    \
-  hipLaunchKernelGGL((KER<ADJ, TNV, KCV, PFV>), grid, dim3(256), 0, st, blk, reinterpret_cast<const WT*>(W), x, \
-                     ld_in, y, ld_out, nrhs, scale, mtiles, ntiles, total)
+#define MBF_LAUNCH(KER, WT, S)                                                                            \
+  hipLaunchKernelGGL((KER<ADJ, S>), grid, dim3(S::NTH), 0, st, blk, reinterpret_cast<const WT*>(W), x, ld_in, \
+                     y, ld_out, nrhs, scale, mtiles, ntiles, total)
   if (prec == MBF_C64) {
     switch (v) {
-      case 0: MBF_LAUNCH(k_stage_f32, float2, 64, 16, false); break;
-      case 1: MBF_LAUNCH(k_stage_f32, float2, 64, 16, true); break;
-      case 2: MBF_LAUNCH(k_stage_f32, float2, 64, 32, false); break;
-      case 3: MBF_LAUNCH(k_stage_f32, float2, 64, 32, true); break;
-      case 4: MBF_LAUNCH(k_stage_f32, float2, 128, 16, true); break;
-      default: MBF_LAUNCH(k_stage_f32, float2, 128, 32, true); break;
+      case 0: MBF_LAUNCH(k_stage_f32, float2, V0); break;
+      case 1: MBF_LAUNCH(k_stage_f32, float2, V1); break;
+      case 2: MBF_LAUNCH(k_stage_f32, float2, V2); break;
+      case 3: MBF_LAUNCH(k_stage_f32, float2, V3); break;
+      case 4: MBF_LAUNCH(k_stage_f32, float2, V4); break;
+      case 5: MBF_LAUNCH(k_stage_f32, float2, V5); break;
+      case 6: MBF_LAUNCH(k_stage_f32, float2, F6); break;
+      default: MBF_LAUNCH(k_stage_f32, float2, F7); break;
     }
   } else {
     switch (v) {
-      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 16, false); break;
-      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 16, true); break;
-      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 32, false); break;
-      case 3: MBF_LAUNCH(k_stage_bf16x3, uint2, 64, 32, true); break;
-      case 4: MBF_LAUNCH(k_stage_bf16x3, uint2, 128, 16, true); break;
-      default: MBF_LAUNCH(k_stage_bf16x3, uint2, 128, 32, true); break;
+      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, V0); break;
+      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, V1); break;
+      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, V2); break;
+      case 3: MBF_LAUNCH(k_stage_bf16x3, uint2, V3); break;
+      case 4: MBF_LAUNCH(k_stage_bf16x3, uint2, V4); break;
+      case 5: MBF_LAUNCH(k_stage_bf16x3, uint2, V5); break;
+      case 6: MBF_LAUNCH(k_stage_bf16x3, uint2, B6); break;
+      default: MBF_LAUNCH(k_stage_bf16x3, uint2, B7); break;
     }
   }
 #undef MBF_LAUNCH
@@ -453,9 +509,9 @@ Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const Block
   const int Qmax = adj ? P.max_M[s] : P.max_K[s];
   if (prec != MBF_C64 && prec != MBF_C64_SPLIT_BF16) return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel"};
   const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, adj, Rmax, Qmax, nrhs);
-  const int tn = variant_tn(v);
-  const int mtiles = std::max(1, (Rmax + TM - 1) / TM);
-  const int ntiles = (nrhs + tn - 1) / tn;
+  const VariantDims vd = variant_dims(prec, v);
+  const int mtiles = std::max(1, (Rmax + vd.tmv - 1) / vd.tmv);
+  const int ntiles = (nrhs + vd.tnv - 1) / vd.tnv;
   const int64_t total = (int64_t)P.nblk[s] * mtiles * ntiles;
   const int64_t grid = (total + kXcd - 1) / kXcd * kXcd;
   if (grid > INT32_MAX) return {MBF_ERR_UNSUPPORTED, "stage grid too large"};
