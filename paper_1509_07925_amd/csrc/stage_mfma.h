@@ -12,8 +12,10 @@ namespace mbf {
 // the split layout).
 bool use_mfma(const DevPart& P, int s, int64_t nrhs, int prec);
 
-// Stage kernel variants (tile shape, reduction chunk, register prefetch).
-constexpr int kNumVariants = 8;
+// Stage kernel variants (tile shape, reduction chunk, register prefetch,
+// LDS buffering): 8 for the FP32 kernels, 10 for the split-BF16 kernels.
+constexpr int kMaxVariants = 10;
+inline int num_variants(int prec) { return prec == MBF_C64 ? 8 : 10; }
 
 // force_variant >= 0 bypasses the tuned choice.
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adjoint, const BlockDesc* blk,

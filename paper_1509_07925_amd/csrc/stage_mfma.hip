@@ -385,6 +385,120 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
   store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
+// BF16 x3 with two LDS buffers: the registers of chunk i+1 are written to
+// one buffer while the matrix cores read chunk i from the other, so one
+// barrier per chunk separates the phases and the waves of a workgroup overlap
+// their LDS writes with the other waves' matrix-core work.  Rows carry no
+// padding; the 16-byte groups of a row are XOR-swizzled with bits 1..2 of
+// the row index, which keeps 8 consecutive rows of a 16-byte read on
+// distinct banks.
+template <bool ADJ, class S>
+__global__ __launch_bounds__(S::NTH) void k_stage_bf16x3_db(const BlockDesc* __restrict__ blk,
+                                                            const uint2* __restrict__ W,
+                                                            const float2* __restrict__ in, int64_t ld_in,
+                                                            float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                            const float* __restrict__ scale, int mtiles,
+                                                            int ntiles, int64_t total) {
+  constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT;
+  static_assert(KC == 16, "swizzle assumes four 16-byte groups per row");
+  __shared__ __attribute__((aligned(16))) uint32_t Ah[2][TNV * KC], Al[2][TNV * KC];
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[2][2 * TMV * KC], Bl[2][2 * TMV * KC];
+  auto sw = [](int r, int k) { return r * KC + ((((k >> 2) ^ (r >> 1)) & 3) << 2) + (k & 3); };
+  const Tile tl = map_tile(total, mtiles, ntiles);
+  if (tl.b < 0) return;
+  const BlockDesc d = blk[tl.b];
+  const int R = ADJ ? d.K : d.M;
+  const int Q = ADJ ? d.M : d.K;
+  const int r0 = tl.mt * TMV;
+  if (r0 >= R) return;
+  const int n0 = tl.nt * TNV;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
+  const uint2* Wb = W + d.w_off;
+  v16f acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
+  Loader<S, ADJ, uint2> ld;
+  auto stash = [&](int buf) {  // registers -> LDS buffer (state split into BF16 hi/lo)
+    const int k = tid % KC, n = tid / KC;
+#pragma unroll
+    for (int j = 0; j < S::EA; ++j) {
+      uint32_t rh, rl, ih, il;
+      split_bf(ld.a[j].x, rh, rl);
+      split_bf(ld.a[j].y, ih, il);
+      const int e = sw(n + j * (NTH / KC), k);
+      Ah[buf][e] = rh | (ih << 16);
+      Al[buf][e] = rl | (il << 16);
+    }
+    if (!ADJ) {
+      const int c = 2 * (tid % TMV), kb = tid / TMV;
+#pragma unroll
+      for (int j = 0; j < S::EB; ++j) {
+        const uint2 w = ld.b[j];
+        const int kk = kb + j * (NTH / TMV);
+        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+        Bh[buf][sw(c, kk)] = reh | ((imh ^ 0x8000u) << 16);
+        Bh[buf][sw(c + 1, kk)] = imh | (reh << 16);
+        Bl[buf][sw(c, kk)] = rel | ((iml ^ 0x8000u) << 16);
+        Bl[buf][sw(c + 1, kk)] = iml | (rel << 16);
+      }
+    } else {
+      const int mr = tid % KC, kp = tid / KC;
+#pragma unroll
+      for (int j = 0; j < S::EB; ++j) {
+        const uint2 w = ld.b[j];
+        const int c = 2 * (kp + j * (NTH / KC));
+        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+        Bh[buf][sw(c, mr)] = reh | (imh << 16);
+        Bh[buf][sw(c + 1, mr)] = (imh ^ 0x8000u) | (reh << 16);
+        Bl[buf][sw(c, mr)] = rel | (iml << 16);
+        Bl[buf][sw(c + 1, mr)] = (iml ^ 0x8000u) | (rel << 16);
+      }
+    }
+  };
+  ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+  stash(0);
+  if (KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KC, nrhs);
+  __syncthreads();
+  const int kh = lane >> 5, li = lane & 31;
+  for (int q0 = 0, cur = 0; q0 < Q; q0 += KC, cur ^= 1) {
+    // Buffer cur^1 was last read before the previous barrier: refill it.
+    if (q0 + KC < Q) {
+      stash(cur ^ 1);
+      if (q0 + 2 * KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KC, nrhs);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KC; kb += 8) {
+      const int ko = kb + 4 * kh;
+      bf16x8 ah[RT], al[RT], bh[CT], bl[CT];
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const int e = sw(wn + 32 * a + li, ko);
+        ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[cur][e]));
+        al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[cur][e]));
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int e = sw(wm + 32 * c + li, ko);
+        bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[cur][e]));
+        bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[cur][e]));
+      }
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
+          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
+          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+}
+
 // Kernel variants: Shape<TNV, TMV, NTH, RT, CT, KC, PF>.
 using V0 = Shape<64, 64, 256, 1, 2, 16, false>;
 using V1 = Shape<64, 64, 256, 1, 2, 16, true>;
@@ -398,6 +512,9 @@ using F7 = Shape<128, 128, 512, 2, 2, 16, true>;
 // BF16 x3 with wide wave tiles (one accumulator set per tile).
 using B6 = Shape<256, 128, 512, 2, 4, 16, true>;
 using B7 = Shape<128, 128, 256, 2, 4, 16, true>;
+// Double-buffered BF16 x3 (k_stage_bf16x3_db).
+using B8 = Shape<256, 128, 512, 2, 4, 16, true>;
+using B9 = Shape<128, 64, 256, 2, 2, 16, true>;
 
 struct VariantDims {
   int tnv, tmv, nth;
@@ -416,7 +533,9 @@ VariantDims variant_dims(int prec, int v) {
     case 4: return dims_of<V4>();
     case 5: return dims_of<V5>();
     case 6: return prec == MBF_C64 ? dims_of<F6>() : dims_of<B6>();
-    default: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B7>();
+    case 7: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B7>();
+    case 8: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B8>();
+    default: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B9>();
   }
 }
 
@@ -452,7 +571,7 @@ void load_tune_file_locked() {
   if (!f) return;
   int a, b, c, d, e, v;
   while (std::fscanf(f, "%d %d %d %d %d %d", &a, &b, &c, &d, &e, &v) == 6)
-    if (v >= 0 && v < kNumVariants) g_tune[TuneKey{a, b, c, d, e}] = v;
+    if (v >= 0 && v < num_variants(a)) g_tune[TuneKey{a, b, c, d, e}] = v;
   std::fclose(f);
 }
 }  // namespace
@@ -464,7 +583,7 @@ int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
   if (it != g_tune.end()) return it->second;
   if (const char* e = std::getenv("MBF_STAGE_VARIANT")) {
     const int v = std::atoi(e);
-    if (v >= 0 && v < kNumVariants) return v;
+    if (v >= 0 && v < num_variants(prec)) return v;
   }
   return prec == MBF_C64 ? 0 : 3;
 }
@@ -496,7 +615,9 @@ static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const Blo
       case 4: MBF_LAUNCH(k_stage_bf16x3, uint2, V4); break;
       case 5: MBF_LAUNCH(k_stage_bf16x3, uint2, V5); break;
       case 6: MBF_LAUNCH(k_stage_bf16x3, uint2, B6); break;
-      default: MBF_LAUNCH(k_stage_bf16x3, uint2, B7); break;
+      case 7: MBF_LAUNCH(k_stage_bf16x3, uint2, B7); break;
+      case 8: MBF_LAUNCH(k_stage_bf16x3_db, uint2, B8); break;
+      default: MBF_LAUNCH(k_stage_bf16x3_db, uint2, B9); break;
     }
   }
 #undef MBF_LAUNCH
@@ -546,7 +667,7 @@ Error autotune_stage(const DevPart& P, int s, int prec, bool adj, const BlockDes
   int best = -1;
   float bt = 0.f;
   Error err{MBF_OK, ""};
-  for (int v = 0; v < kNumVariants && err.st == MBF_OK; ++v) {
+  for (int v = 0; v < num_variants(prec) && err.st == MBF_OK; ++v) {
     err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, v);
     if (err.st != MBF_OK) break;
     (void)hipEventRecord(e0, st);
