@@ -12,10 +12,9 @@ namespace mbf {
 // the split layout).
 bool use_mfma(const DevPart& P, int s, int64_t nrhs, int prec);
 
-// Stage kernel variants (tile shape, reduction chunk, register prefetch,
-// LDS buffering): 8 for the FP32 kernels, 10 for the split-BF16 kernels.
-constexpr int kMaxVariants = 10;
-inline int num_variants(int prec) { return prec == MBF_C64 ? 8 : 10; }
+// Stage kernel variants (tile shape, register prefetch, LDS buffering):
+// 6 for the FP32 kernels, 7 for the split-BF16 kernels.
+inline int num_variants(int prec) { return prec == MBF_C64 ? 6 : 7; }
 
 // force_variant >= 0 bypasses the tuned choice.
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adjoint, const BlockDesc* blk,

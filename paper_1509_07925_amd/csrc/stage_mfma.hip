@@ -82,22 +82,39 @@ __device__ __forceinline__ Tile map_tile(int64_t total, int mtiles, int ntiles) 
   return r;
 }
 
+constexpr int KCH = 16;      // reduction chunk (complex entries) of every variant
+constexpr int PA = KCH + 4;  // LDS pitch (words) of the state operand rows
+
+// LDS word of (output row mrow, real/imaginary output column d, 4-word group
+// g of the chunk) in the block operand.  Each output row holds 2 x 16 words;
+// the 16-byte groups are XOR-swizzled by the row so that the 16-byte reads of
+// 32 consecutive real columns, and the 16-byte writes of consecutive rows,
+// spread over the banks (conflict-free reads, at most 2-way writes).
+__device__ __forceinline__ int bidx(int mrow, int d, int g) {
+  return mrow * (2 * KCH) + d * KCH + (((g ^ mrow ^ (mrow >> 2)) & 3) << 2);
+}
+
+// Padded alternative for the FP32 kernels (whose LDS budget allows it): one
+// row of PA words per real output column 2 mrow + d; 16-byte reads of
+// consecutive rows are conflict-free and the offsets fold into immediates.
+__device__ __forceinline__ int bidx_pad(int mrow, int d, int g) { return (2 * mrow + d) * PA + 4 * g; }
+
 // Tile shape of a kernel variant: TNV right-hand sides x TMV complex output
 // rows per workgroup of NTH threads; each wave owns RT x CT matrix-core tiles
-// of 32 right-hand sides x 32 real columns; the reduction runs in chunks of
-// KC complex entries, with register prefetch of the next chunk when PF.
-template <int TNV_, int TMV_, int NTH_, int RT_, int CT_, int KC_, bool PF_>
+// of 32 right-hand sides x 32 real columns.  PF prefetches the next chunk
+// into registers during the matrix-core work; DB (which implies PF) also
+// double-buffers the LDS so that one barrier per chunk separates the phases.
+template <int TNV_, int TMV_, int NTH_, int RT_, int CT_, bool PF_, bool DB_>
 struct Shape {
-  static constexpr int TNV = TNV_, TMV = TMV_, NTH = NTH_, RT = RT_, CT = CT_, KC = KC_;
-  static constexpr bool PF = PF_;
+  static constexpr int TNV = TNV_, TMV = TMV_, NTH = NTH_, RT = RT_, CT = CT_;
+  static constexpr bool PF = PF_ || DB_, DB = DB_;
   static constexpr int WR = TNV / (32 * RT);      // waves along right-hand sides
   static constexpr int WC = 2 * TMV / (32 * CT);  // waves along real columns
   static_assert(WR * WC * 64 == NTH, "the waves must cover the tile");
-  static constexpr int EA = TNV * KC / NTH;  // state entries per thread per chunk
-  static constexpr int EB = TMV * KC / NTH;  // block entries per thread per chunk
-  static_assert(EA * NTH == TNV * KC && EB * NTH == TMV * KC, "load mapping");
-  static_assert(NTH % KC == 0 && NTH % TMV == 0 && KC % (NTH / TMV) == 0, "load mapping");
-  static constexpr int P = KC + 4;  // LDS row pitch in words (16-byte aligned rows)
+  static constexpr int EA = TNV * KCH / NTH;  // state entries per thread per chunk
+  static constexpr int EB = TMV * 4 / NTH;    // (row, group) pairs of the block per thread per chunk
+  static_assert(EA * NTH == TNV * KCH && EB * NTH == TMV * 4 && NTH % KCH == 0, "load mapping");
+  static constexpr int NB = DB ? 2 : 1;  // LDS buffers
 };
 
 // Store the wave's RT x CT accumulator tiles (32 x 32 real each): rows are
@@ -127,61 +144,75 @@ __device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int
 }
 
 // ------------------------------------------------------------------ loads
-// Each chunk moves a TNV x KC tile of the input state (A) and a KC x TMV
-// tile of the block (B) into registers, with consecutive lanes on
-// consecutive memory (the reduction index for A and for the adjoint's B, the
-// output index for the forward B).  With PF the registers for the next chunk
-// are loaded while the matrix cores work on the current one.
-//   A:             k = tid % KC,  n = tid / KC + j (NTH / KC)
-//   B (forward):   m = tid % TMV, k = tid / TMV + j (NTH / TMV)
-//   B (adjoint):   m' = tid % KC, k' = tid / KC + j (NTH / KC)
+// Each chunk moves a TNV x 16 tile of the input state (A) and a 16 x TMV
+// tile of the block (B) into registers, consecutive lanes on consecutive
+// memory:
+//   A:            k = tid % 16, n = tid / 16 + j (NTH / 16)
+//   B forward:    pair p = tid + j NTH: row m = p % TMV, group g = p / TMV;
+//                 the 4 entries W(m, 4g .. 4g+3) (lanes along m)
+//   B adjoint:    pair p = tid + j NTH: group g = p % 4, row k' = p / 4;
+//                 the 4 entries W(4g .. 4g+3, k') (contiguous)
 template <class S, bool ADJ, typename WT>
 struct Loader {
   float2 a[S::EA];
-  WT b[S::EB];
+  WT b[S::EB][4];
   __device__ __forceinline__ void load(const BlockDesc& d, const float2* __restrict__ in, int64_t ld_in,
                                        const WT* __restrict__ Wb, int R, int Q, int r0, int n0, int q0,
                                        int nrhs) {
-    constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV;
+    constexpr int NTH = S::NTH, TMV = S::TMV;
     const int tid = threadIdx.x;
     {
-      const int k = tid % KC, n = tid / KC;
+      const int k = tid % KCH, n = tid / KCH;
       const int q = q0 + k;
       int32_t row = 0;
       if (q < Q) row = ADJ ? grp_row(d, q) : d.in_row + q;
 #pragma unroll
       for (int j = 0; j < S::EA; ++j) {
-        const int gn = n0 + n + j * (NTH / KC);
+        const int gn = n0 + n + j * (NTH / KCH);
         float2 v = make_float2(0.f, 0.f);
         if (gn < nrhs && q < Q) v = in[(int64_t)gn * ld_in + row];
         a[j] = v;
       }
     }
+#pragma unroll
+    for (int j = 0; j < S::EB; ++j) {
+      const int p = tid + j * NTH;
+      if (!ADJ) {
+        const int m = r0 + p % TMV, q = q0 + 4 * (p / TMV);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          WT w{};
+          if (m < R && q + i < Q) w = Wb[(int64_t)(q + i) * d.M + m];
+          b[j][i] = w;
+        }
+      } else {
+        const int mr = q0 + 4 * (p % 4), kout = r0 + p / 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          WT w{};
+          if (kout < R && mr + i < Q) w = Wb[(int64_t)kout * d.M + mr + i];
+          b[j][i] = w;
+        }
+      }
+    }
+  }
+  // LDS row and group of pair j.
+  __device__ __forceinline__ static void pair_pos(int j, int& mrow, int& g) {
+    const int p = threadIdx.x + j * S::NTH;
     if (!ADJ) {
-      const int m = r0 + tid % TMV, kb = tid / TMV;
-#pragma unroll
-      for (int j = 0; j < S::EB; ++j) {
-        const int q = q0 + kb + j * (NTH / TMV);
-        WT w{};
-        if (m < R && q < Q) w = Wb[(int64_t)q * d.M + m];
-        b[j] = w;
-      }
+      mrow = p % S::TMV;
+      g = p / S::TMV;
     } else {
-      const int mr = q0 + tid % KC, kp = tid / KC;
-#pragma unroll
-      for (int j = 0; j < S::EB; ++j) {
-        const int kout = r0 + kp + j * (NTH / KC);
-        WT w{};
-        if (kout < R && mr < Q) w = Wb[(int64_t)kout * d.M + mr];
-        b[j] = w;
-      }
+      mrow = p / 4;
+      g = p % 4;
     }
   }
 };
 
 // ------------------------------------------------------------------ FP32
 // Wave w covers right-hand sides wn = (w % WR) * 32 RT and real columns
-// wm = (w / WR) * 32 CT.
+// wm = (w / WR) * 32 CT.  One MFMA consumes one complex k: lanes 0-31 the
+// real parts (plane 0), lanes 32-63 the imaginary parts (plane 1).
 template <bool ADJ, class S>
 __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restrict__ blk,
                                                       const float2* __restrict__ W,
@@ -189,9 +220,9 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
                                                       float2* __restrict__ out, int64_t ld_out, int nrhs,
                                                       const float* __restrict__ scale, int mtiles, int ntiles,
                                                       int64_t total) {
-  constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV, P = S::P, RT = S::RT, CT = S::CT;
-  __shared__ __attribute__((aligned(16))) float As[2][S::TNV][P];  // [re|im][n][k]
-  __shared__ __attribute__((aligned(16))) float Bs[2][2 * TMV][P];  // [c][real col][k]
+  constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
+  __shared__ __attribute__((aligned(16))) float As[NB][2][TNV * PA];        // [buf][re|im][n][k]
+  __shared__ __attribute__((aligned(16))) float Bs[NB][2][2 * TMV * PA];  // [buf][plane][bidx_pad]
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
   const BlockDesc d = blk[tl.b];
@@ -199,10 +230,34 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
   const int Q = ADJ ? d.M : d.K;
   const int r0 = tl.mt * TMV;
   if (r0 >= R) return;
-  const int n0 = tl.nt * S::TNV;
+  const int n0 = tl.nt * TNV;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
   const float2* Wb = W + d.w_off;
+  using LD = Loader<S, ADJ, float2>;
+  LD ld;
+  auto stash = [&](int buf) {
+    const int k = tid % KCH, n = tid / KCH;
+#pragma unroll
+    for (int j = 0; j < S::EA; ++j) {
+      As[buf][0][(n + j * (NTH / KCH)) * PA + k] = ld.a[j].x;
+      As[buf][1][(n + j * (NTH / KCH)) * PA + k] = ld.a[j].y;
+    }
+#pragma unroll
+    for (int j = 0; j < S::EB; ++j) {
+      int mrow, g;
+      LD::pair_pos(j, mrow, g);
+      const float2* w = ld.b[j];
+      // forward B(2k+c, 2m+d): c=0: (Wr, Wi), c=1: (-Wi, Wr); the adjoint uses conj(W)
+      const float s = ADJ ? -1.f : 1.f;
+      *reinterpret_cast<float4*>(&Bs[buf][0][bidx_pad(mrow, 0, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
+      *reinterpret_cast<float4*>(&Bs[buf][0][bidx_pad(mrow, 1, g)]) =
+          make_float4(s * w[0].y, s * w[1].y, s * w[2].y, s * w[3].y);
+      *reinterpret_cast<float4*>(&Bs[buf][1][bidx_pad(mrow, 0, g)]) =
+          make_float4(-s * w[0].y, -s * w[1].y, -s * w[2].y, -s * w[3].y);
+      *reinterpret_cast<float4*>(&Bs[buf][1][bidx_pad(mrow, 1, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
+    }
+  };
   // Two-level summation: the matrix cores sum one chunk into p, which is then
   // added to the running sums; the rounding error grows with the chunk
   // length plus the number of chunks instead of with the full reduction.
@@ -211,56 +266,24 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
-  Loader<S, ADJ, float2> ld;
-  if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-  for (int q0 = 0; q0 < Q; q0 += KC) {
-    if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
-    {  // registers -> LDS
-      const int k = tid % KC, n = tid / KC;
-#pragma unroll
-      for (int j = 0; j < S::EA; ++j) {
-        As[0][n + j * (NTH / KC)][k] = ld.a[j].x;
-        As[1][n + j * (NTH / KC)][k] = ld.a[j].y;
-      }
-      if (!ADJ) {
-        const int c = 2 * (tid % TMV), kb = tid / TMV;
-#pragma unroll
-        for (int j = 0; j < S::EB; ++j) {
-          const float2 w = ld.b[j];
-          const int kk = kb + j * (NTH / TMV);
-          Bs[0][c][kk] = w.x;
-          Bs[0][c + 1][kk] = w.y;
-          Bs[1][c][kk] = -w.y;
-          Bs[1][c + 1][kk] = w.x;
-        }
-      } else {
-        const int mr = tid % KC, kp = tid / KC;
-#pragma unroll
-        for (int j = 0; j < S::EB; ++j) {
-          const float2 w = ld.b[j];
-          const int c = 2 * (kp + j * (NTH / KC));
-          Bs[0][c][mr] = w.x;
-          Bs[0][c + 1][mr] = -w.y;
-          Bs[1][c][mr] = w.y;
-          Bs[1][c + 1][mr] = w.x;
-        }
-      }
-    }
-    __syncthreads();
-    if (S::PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
-    const int kk = lane >> 5, li = lane & 31;
+  const int kk = lane >> 5, li = lane & 31;
+  auto compute = [&](int buf) {
     v16f p[RT][CT];
 #pragma unroll
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int c = 0; c < CT; ++c) p[a][c] = v16f{};
 #pragma unroll
-    for (int kb = 0; kb < KC; kb += 4) {
+    for (int kb = 0; kb < KCH; kb += 4) {
       float4 av[RT], bv[CT];
 #pragma unroll
-      for (int a = 0; a < RT; ++a) av[a] = *reinterpret_cast<const float4*>(&As[kk][wn + 32 * a + li][kb]);
+      for (int a = 0; a < RT; ++a)
+        av[a] = *reinterpret_cast<const float4*>(&As[buf][kk][(wn + 32 * a + li) * PA + kb]);
 #pragma unroll
-      for (int c = 0; c < CT; ++c) bv[c] = *reinterpret_cast<const float4*>(&Bs[kk][wm + 32 * c + li][kb]);
+      for (int c = 0; c < CT; ++c) {
+        const int col = wm + 32 * c + li;
+        bv[c] = *reinterpret_cast<const float4*>(&Bs[buf][kk][bidx_pad(col >> 1, col & 1, kb >> 2)]);
+      }
 #pragma unroll
       for (int a = 0; a < RT; ++a)
 #pragma unroll
@@ -275,16 +298,40 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
     for (int a = 0; a < RT; ++a)
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[a][c] += p[a][c];
+  };
+  if (S::DB) {
+    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    stash(0);
+    if (KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
     __syncthreads();
+    for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
+      // Buffer cur^1 was last read before the previous barrier: refill it.
+      if (q0 + KCH < Q) {
+        stash(cur ^ 1);
+        if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+      }
+      compute(cur);
+      __syncthreads();
+    }
+  } else {
+    if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    for (int q0 = 0; q0 < Q; q0 += KCH) {
+      if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+      stash(0);
+      __syncthreads();
+      if (S::PF && q0 + KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
+      compute(0);
+      __syncthreads();
+    }
   }
   store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
 // ------------------------------------------------------------------ BF16 x3
-// LDS rows hold interleaved pairs along the complex reduction index: entry
-// (row, k) is one 32-bit word = two BF16 values (real-k 2k and 2k+1).  The
-// split products carry ~2^-16 relative error, so the partial sums go straight
-// into the matrix-core accumulators (no compensation).
+// LDS words hold two BF16 values along the reduction: the state word (n, k)
+// is (Re, Im) of x(n, k); the block words are the matching pairs of the
+// embedding.  The split products carry ~2^-16 relative error, so the partial
+// sums go straight into the matrix-core accumulators (no compensation).
 template <bool ADJ, class S>
 __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __restrict__ blk,
                                                          const uint2* __restrict__ W,  // (re_hi,im_hi | re_lo,im_lo)
@@ -292,118 +339,9 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
                                                          float2* __restrict__ out, int64_t ld_out, int nrhs,
                                                          const float* __restrict__ scale, int mtiles, int ntiles,
                                                          int64_t total) {
-  constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV, P = S::P, RT = S::RT, CT = S::CT;
-  __shared__ __attribute__((aligned(16))) uint32_t Ah[S::TNV][P], Al[S::TNV][P];
-  __shared__ __attribute__((aligned(16))) uint32_t Bh[2 * TMV][P], Bl[2 * TMV][P];
-  const Tile tl = map_tile(total, mtiles, ntiles);
-  if (tl.b < 0) return;
-  const BlockDesc d = blk[tl.b];
-  const int R = ADJ ? d.K : d.M;
-  const int Q = ADJ ? d.M : d.K;
-  const int r0 = tl.mt * TMV;
-  if (r0 >= R) return;
-  const int n0 = tl.nt * S::TNV;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
-  const uint2* Wb = W + d.w_off;
-  v16f acc[RT][CT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
-  Loader<S, ADJ, uint2> ld;
-  if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-  for (int q0 = 0; q0 < Q; q0 += KC) {
-    if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
-    {  // registers -> LDS (state split into BF16 hi/lo here)
-      const int k = tid % KC, n = tid / KC;
-#pragma unroll
-      for (int j = 0; j < S::EA; ++j) {
-        uint32_t rh, rl, ih, il;
-        split_bf(ld.a[j].x, rh, rl);
-        split_bf(ld.a[j].y, ih, il);
-        Ah[n + j * (NTH / KC)][k] = rh | (ih << 16);
-        Al[n + j * (NTH / KC)][k] = rl | (il << 16);
-      }
-      if (!ADJ) {
-        const int c = 2 * (tid % TMV), kb = tid / TMV;
-#pragma unroll
-        for (int j = 0; j < S::EB; ++j) {
-          const uint2 w = ld.b[j];
-          const int kk = kb + j * (NTH / TMV);
-          const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-          // column 2m (real part): (Wr, -Wi);  column 2m+1 (imag part): (Wi, Wr)
-          Bh[c][kk] = reh | ((imh ^ 0x8000u) << 16);
-          Bh[c + 1][kk] = imh | (reh << 16);
-          Bl[c][kk] = rel | ((iml ^ 0x8000u) << 16);
-          Bl[c + 1][kk] = iml | (rel << 16);
-        }
-      } else {
-        const int mr = tid % KC, kp = tid / KC;
-#pragma unroll
-        for (int j = 0; j < S::EB; ++j) {
-          const uint2 w = ld.b[j];
-          const int c = 2 * (kp + j * (NTH / KC));
-          const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-          // conj(W): column 2k' (real part): (Wr, Wi);  column 2k'+1 (imag part): (-Wi, Wr)
-          Bh[c][mr] = reh | (imh << 16);
-          Bh[c + 1][mr] = (imh ^ 0x8000u) | (reh << 16);
-          Bl[c][mr] = rel | (iml << 16);
-          Bl[c + 1][mr] = (iml ^ 0x8000u) | (rel << 16);
-        }
-      }
-    }
-    __syncthreads();
-    if (S::PF && q0 + KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KC, nrhs);
-    const int kh = lane >> 5, li = lane & 31;
-#pragma unroll
-    for (int kb = 0; kb < KC; kb += 8) {
-      // lane holds real-k 8*kh .. 8*kh+7 of this step = complex k kb + 4*kh .. +3
-      const int ko = kb + 4 * kh;
-      bf16x8 ah[RT], al[RT], bh[CT], bl[CT];
-#pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[wn + 32 * a + li][ko]));
-        al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[wn + 32 * a + li][ko]));
-      }
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[wm + 32 * c + li][ko]));
-        bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[wm + 32 * c + li][ko]));
-      }
-#pragma unroll
-      for (int a = 0; a < RT; ++a)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
-          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
-          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-  }
-  store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
-}
-
-// BF16 x3 with two LDS buffers: the registers of chunk i+1 are written to
-// one buffer while the matrix cores read chunk i from the other, so one
-// barrier per chunk separates the phases and the waves of a workgroup overlap
-// their LDS writes with the other waves' matrix-core work.  Rows carry no
-// padding; the 16-byte groups of a row are XOR-swizzled with bits 1..2 of
-// the row index, which keeps 8 consecutive rows of a 16-byte read on
-// distinct banks.
-template <bool ADJ, class S>
-__global__ __launch_bounds__(S::NTH) void k_stage_bf16x3_db(const BlockDesc* __restrict__ blk,
-                                                            const uint2* __restrict__ W,
-                                                            const float2* __restrict__ in, int64_t ld_in,
-                                                            float2* __restrict__ out, int64_t ld_out, int nrhs,
-                                                            const float* __restrict__ scale, int mtiles,
-                                                            int ntiles, int64_t total) {
-  constexpr int KC = S::KC, NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT;
-  static_assert(KC == 16, "swizzle assumes four 16-byte groups per row");
-  __shared__ __attribute__((aligned(16))) uint32_t Ah[2][TNV * KC], Al[2][TNV * KC];
-  __shared__ __attribute__((aligned(16))) uint32_t Bh[2][2 * TMV * KC], Bl[2][2 * TMV * KC];
-  auto sw = [](int r, int k) { return r * KC + ((((k >> 2) ^ (r >> 1)) & 3) << 2) + (k & 3); };
+  constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
+  __shared__ __attribute__((aligned(16))) uint32_t Ah[NB][TNV * PA], Al[NB][TNV * PA];
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[NB][TMV * 2 * KCH], Bl[NB][TMV * 2 * KCH];
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
   const BlockDesc d = blk[tl.b];
@@ -415,75 +353,69 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3_db(const BlockDesc* __r
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
   const uint2* Wb = W + d.w_off;
-  v16f acc[RT][CT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
-  Loader<S, ADJ, uint2> ld;
-  auto stash = [&](int buf) {  // registers -> LDS buffer (state split into BF16 hi/lo)
-    const int k = tid % KC, n = tid / KC;
+  using LD = Loader<S, ADJ, uint2>;
+  LD ld;
+  auto stash = [&](int buf) {  // registers -> LDS (state split into BF16 hi/lo here)
+    const int k = tid % KCH, n = tid / KCH;
 #pragma unroll
     for (int j = 0; j < S::EA; ++j) {
       uint32_t rh, rl, ih, il;
       split_bf(ld.a[j].x, rh, rl);
       split_bf(ld.a[j].y, ih, il);
-      const int e = sw(n + j * (NTH / KC), k);
-      Ah[buf][e] = rh | (ih << 16);
-      Al[buf][e] = rl | (il << 16);
+      Ah[buf][(n + j * (NTH / KCH)) * PA + k] = rh | (ih << 16);
+      Al[buf][(n + j * (NTH / KCH)) * PA + k] = rl | (il << 16);
     }
-    if (!ADJ) {
-      const int c = 2 * (tid % TMV), kb = tid / TMV;
 #pragma unroll
-      for (int j = 0; j < S::EB; ++j) {
-        const uint2 w = ld.b[j];
-        const int kk = kb + j * (NTH / TMV);
-        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-        Bh[buf][sw(c, kk)] = reh | ((imh ^ 0x8000u) << 16);
-        Bh[buf][sw(c + 1, kk)] = imh | (reh << 16);
-        Bl[buf][sw(c, kk)] = rel | ((iml ^ 0x8000u) << 16);
-        Bl[buf][sw(c + 1, kk)] = iml | (rel << 16);
-      }
-    } else {
-      const int mr = tid % KC, kp = tid / KC;
+    for (int j = 0; j < S::EB; ++j) {
+      int mrow, g;
+      LD::pair_pos(j, mrow, g);
+      uint32_t h0[4], h1[4], l0[4], l1[4];
 #pragma unroll
-      for (int j = 0; j < S::EB; ++j) {
-        const uint2 w = ld.b[j];
-        const int c = 2 * (kp + j * (NTH / KC));
+      for (int i = 0; i < 4; ++i) {
+        const uint2 w = ld.b[j][i];
         const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-        Bh[buf][sw(c, mr)] = reh | (imh << 16);
-        Bh[buf][sw(c + 1, mr)] = (imh ^ 0x8000u) | (reh << 16);
-        Bl[buf][sw(c, mr)] = rel | (iml << 16);
-        Bl[buf][sw(c + 1, mr)] = (iml ^ 0x8000u) | (rel << 16);
+        if (!ADJ) {  // column 2m: (Wr, -Wi);  column 2m+1: (Wi, Wr)
+          h0[i] = reh | ((imh ^ 0x8000u) << 16);
+          h1[i] = imh | (reh << 16);
+          l0[i] = rel | ((iml ^ 0x8000u) << 16);
+          l1[i] = iml | (rel << 16);
+        } else {  // conj(W): column 2k': (Wr, Wi);  column 2k'+1: (-Wi, Wr)
+          h0[i] = reh | (imh << 16);
+          h1[i] = (imh ^ 0x8000u) | (reh << 16);
+          l0[i] = rel | (iml << 16);
+          l1[i] = (iml ^ 0x8000u) | (rel << 16);
+        }
       }
+      *reinterpret_cast<uint4*>(&Bh[buf][bidx(mrow, 0, g)]) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+      *reinterpret_cast<uint4*>(&Bh[buf][bidx(mrow, 1, g)]) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+      *reinterpret_cast<uint4*>(&Bl[buf][bidx(mrow, 0, g)]) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+      *reinterpret_cast<uint4*>(&Bl[buf][bidx(mrow, 1, g)]) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
     }
   };
-  ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-  stash(0);
-  if (KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KC, nrhs);
-  __syncthreads();
-  const int kh = lane >> 5, li = lane & 31;
-  for (int q0 = 0, cur = 0; q0 < Q; q0 += KC, cur ^= 1) {
-    // Buffer cur^1 was last read before the previous barrier: refill it.
-    if (q0 + KC < Q) {
-      stash(cur ^ 1);
-      if (q0 + 2 * KC < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KC, nrhs);
-    }
+  v16f acc[RT][CT];
 #pragma unroll
-    for (int kb = 0; kb < KC; kb += 8) {
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
+  const int kh = lane >> 5, li = lane & 31;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kb = 0; kb < KCH; kb += 8) {
+      // lane holds real-k 8*kh .. 8*kh+7 of this step = complex k kb + 4*kh .. +3
       const int ko = kb + 4 * kh;
       bf16x8 ah[RT], al[RT], bh[CT], bl[CT];
 #pragma unroll
       for (int a = 0; a < RT; ++a) {
-        const int e = sw(wn + 32 * a + li, ko);
-        ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[cur][e]));
-        al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[cur][e]));
+        const int e = (wn + 32 * a + li) * PA + ko;
+        ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[buf][e]));
+        al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[buf][e]));
       }
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const int e = sw(wm + 32 * c + li, ko);
-        bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[cur][e]));
-        bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[cur][e]));
+        const int col = wm + 32 * c + li;
+        const int e = bidx(col >> 1, col & 1, ko >> 2);
+        bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[buf][e]));
+        bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[buf][e]));
       }
 #pragma unroll
       for (int a = 0; a < RT; ++a)
@@ -494,27 +426,49 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3_db(const BlockDesc* __r
           acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
         }
     }
+  };
+  if (S::DB) {
+    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    stash(0);
+    if (KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
     __syncthreads();
+    for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
+      // Buffer cur^1 was last read before the previous barrier: refill it.
+      if (q0 + KCH < Q) {
+        stash(cur ^ 1);
+        if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+      }
+      compute(cur);
+      __syncthreads();
+    }
+  } else {
+    if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    for (int q0 = 0; q0 < Q; q0 += KCH) {
+      if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+      stash(0);
+      __syncthreads();
+      if (S::PF && q0 + KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
+      compute(0);
+      __syncthreads();
+    }
   }
   store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
-// Kernel variants: Shape<TNV, TMV, NTH, RT, CT, KC, PF>.
-using V0 = Shape<64, 64, 256, 1, 2, 16, false>;
-using V1 = Shape<64, 64, 256, 1, 2, 16, true>;
-using V2 = Shape<64, 64, 256, 1, 2, 32, false>;
-using V3 = Shape<64, 64, 256, 1, 2, 32, true>;
-using V4 = Shape<128, 64, 256, 2, 2, 16, true>;
-using V5 = Shape<128, 64, 256, 2, 2, 32, true>;
-// FP32 with 8 waves (two accumulator sets per tile bound the wave tile).
-using F6 = Shape<256, 64, 512, 2, 2, 16, true>;
-using F7 = Shape<128, 128, 512, 2, 2, 16, true>;
-// BF16 x3 with wide wave tiles (one accumulator set per tile).
-using B6 = Shape<256, 128, 512, 2, 4, 16, true>;
-using B7 = Shape<128, 128, 256, 2, 4, 16, true>;
-// Double-buffered BF16 x3 (k_stage_bf16x3_db).
-using B8 = Shape<256, 128, 512, 2, 4, 16, true>;
-using B9 = Shape<128, 64, 256, 2, 2, 16, true>;
+// Kernel variants: Shape<TNV, TMV, NTH, RT, CT, PF, DB>.
+using F0 = Shape<64, 64, 256, 1, 2, false, false>;
+using F1 = Shape<64, 64, 256, 1, 2, true, false>;
+using F2 = Shape<128, 64, 256, 2, 2, true, false>;
+using F3 = Shape<64, 64, 256, 1, 2, true, true>;
+using F4 = Shape<128, 64, 256, 2, 2, true, true>;
+using F5 = Shape<128, 128, 512, 2, 2, true, true>;
+using B0 = Shape<64, 64, 256, 1, 2, false, false>;
+using B1 = Shape<128, 64, 256, 2, 2, true, false>;
+using B2 = Shape<256, 128, 512, 2, 4, true, false>;
+using B3 = Shape<128, 128, 256, 2, 4, true, false>;
+using B4 = Shape<128, 64, 256, 2, 2, true, true>;
+using B5 = Shape<256, 128, 512, 2, 4, true, true>;
+using B6 = Shape<128, 128, 256, 2, 4, true, true>;
 
 struct VariantDims {
   int tnv, tmv, nth;
@@ -525,17 +479,24 @@ constexpr VariantDims dims_of() {
 }
 
 VariantDims variant_dims(int prec, int v) {
+  if (prec == MBF_C64) {
+    switch (v) {
+      case 0: return dims_of<F0>();
+      case 1: return dims_of<F1>();
+      case 2: return dims_of<F2>();
+      case 3: return dims_of<F3>();
+      case 4: return dims_of<F4>();
+      default: return dims_of<F5>();
+    }
+  }
   switch (v) {
-    case 0: return dims_of<V0>();
-    case 1: return dims_of<V1>();
-    case 2: return dims_of<V2>();
-    case 3: return dims_of<V3>();
-    case 4: return dims_of<V4>();
-    case 5: return dims_of<V5>();
-    case 6: return prec == MBF_C64 ? dims_of<F6>() : dims_of<B6>();
-    case 7: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B7>();
-    case 8: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B8>();
-    default: return prec == MBF_C64 ? dims_of<F7>() : dims_of<B9>();
+    case 0: return dims_of<B0>();
+    case 1: return dims_of<B1>();
+    case 2: return dims_of<B2>();
+    case 3: return dims_of<B3>();
+    case 4: return dims_of<B4>();
+    case 5: return dims_of<B5>();
+    default: return dims_of<B6>();
   }
 }
 
@@ -585,7 +546,10 @@ int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
     const int v = std::atoi(e);
     if (v >= 0 && v < num_variants(prec)) return v;
   }
-  return prec == MBF_C64 ? 0 : 3;
+  // Untuned defaults: the small FP32 tile; for BF16 x3 the double-buffered
+  // 256 x 128 tile when the right-hand sides fill it, else 128 x 64.
+  if (prec == MBF_C64) return 0;
+  return nrhs >= 192 ? 5 : 4;
 }
 
 template <bool ADJ>
@@ -597,27 +561,22 @@ static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const Blo
                      y, ld_out, nrhs, scale, mtiles, ntiles, total)
   if (prec == MBF_C64) {
     switch (v) {
-      case 0: MBF_LAUNCH(k_stage_f32, float2, V0); break;
-      case 1: MBF_LAUNCH(k_stage_f32, float2, V1); break;
-      case 2: MBF_LAUNCH(k_stage_f32, float2, V2); break;
-      case 3: MBF_LAUNCH(k_stage_f32, float2, V3); break;
-      case 4: MBF_LAUNCH(k_stage_f32, float2, V4); break;
-      case 5: MBF_LAUNCH(k_stage_f32, float2, V5); break;
-      case 6: MBF_LAUNCH(k_stage_f32, float2, F6); break;
-      default: MBF_LAUNCH(k_stage_f32, float2, F7); break;
+      case 0: MBF_LAUNCH(k_stage_f32, float2, F0); break;
+      case 1: MBF_LAUNCH(k_stage_f32, float2, F1); break;
+      case 2: MBF_LAUNCH(k_stage_f32, float2, F2); break;
+      case 3: MBF_LAUNCH(k_stage_f32, float2, F3); break;
+      case 4: MBF_LAUNCH(k_stage_f32, float2, F4); break;
+      default: MBF_LAUNCH(k_stage_f32, float2, F5); break;
     }
   } else {
     switch (v) {
-      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, V0); break;
-      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, V1); break;
-      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, V2); break;
-      case 3: MBF_LAUNCH(k_stage_bf16x3, uint2, V3); break;
-      case 4: MBF_LAUNCH(k_stage_bf16x3, uint2, V4); break;
-      case 5: MBF_LAUNCH(k_stage_bf16x3, uint2, V5); break;
-      case 6: MBF_LAUNCH(k_stage_bf16x3, uint2, B6); break;
-      case 7: MBF_LAUNCH(k_stage_bf16x3, uint2, B7); break;
-      case 8: MBF_LAUNCH(k_stage_bf16x3_db, uint2, B8); break;
-      default: MBF_LAUNCH(k_stage_bf16x3_db, uint2, B9); break;
+      case 0: MBF_LAUNCH(k_stage_bf16x3, uint2, B0); break;
+      case 1: MBF_LAUNCH(k_stage_bf16x3, uint2, B1); break;
+      case 2: MBF_LAUNCH(k_stage_bf16x3, uint2, B2); break;
+      case 3: MBF_LAUNCH(k_stage_bf16x3, uint2, B3); break;
+      case 4: MBF_LAUNCH(k_stage_bf16x3, uint2, B4); break;
+      case 5: MBF_LAUNCH(k_stage_bf16x3, uint2, B5); break;
+      default: MBF_LAUNCH(k_stage_bf16x3, uint2, B6); break;
     }
   }
 #undef MBF_LAUNCH
