@@ -122,10 +122,12 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: multi-GPU runs are not part of this build "
+        print("bench.py measures one GPU; multi-GPU runs are not implemented "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    # Long builds report progress on stderr (at most every 10 s).
+    os.environ.setdefault("MBF_VERBOSE", "1")
     import numpy as np
     import torch
 

@@ -329,10 +329,12 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
 
   // ---------------- U tasks: one per middle-level X node
   Progress pu("U pass", xt.nn(m)), pv("V pass", ot.nn(L - m));
+  Progress pm("middle-level pairs", (int64_t)xt.nn(m) * ot.nn(L - m));
   parallel_for(xt.nn(m), threads, [&](int64_t ia_m) {
     std::map<std::pair<int32_t, int32_t>, Mat> U;  // (ia, ib) at current stage
     for (int32_t ib = 0; ib < ot.nn(L - m); ++ib) {
       Low lw = middle_pair(c, xt, ot, m, (int32_t)ia_m, ib, o, q0);
+      pm.tick();
       const int64_t r = (int64_t)lw.s.size();
       Mat Uf = lw.U0;
       for (int64_t j = 0; j < r; ++j)
