@@ -15,6 +15,7 @@
 
 #include "device.h"
 #include "stage_mfma.h"
+#include "stage_narrow.h"
 
 namespace mbf {
 
@@ -454,6 +455,10 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
         Error e = launch_stage_mfma(P, s, prec, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1],
                                     P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
+      } else if (prec == MBF_C64) {
+        Error e = launch_stage_narrow(P, s, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1],
+                                      ni, reinterpret_cast<const float*>(sc), st);
+        if (e.st != MBF_OK) return e;
       } else {
         hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[s & 1],
                            P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni, sc);
@@ -480,6 +485,10 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
         Error e = launch_stage_mfma(P, s, prec, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
                                     P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
+        if (e.st != MBF_OK) return e;
+      } else if (prec == MBF_C64) {
+        Error e = launch_stage_narrow(P, s, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s],
+                                      ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
         hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[(s + 1) & 1],

@@ -547,9 +547,10 @@ int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
     if (v >= 0 && v < num_variants(prec)) return v;
   }
   // Untuned defaults: the small FP32 tile; for BF16 x3 the double-buffered
-  // 256 x 128 tile when the right-hand sides fill it, else 128 x 64.
+  // 256 x 128 tile when the right-hand sides fill it, the 128 x 64 one for
+  // mid-size batches, the 64 x 64 one for small batches.
   if (prec == MBF_C64) return 0;
-  return nrhs >= 192 ? 5 : 4;
+  return nrhs >= 192 ? 5 : nrhs > 64 ? 4 : 0;
 }
 
 template <bool ADJ>

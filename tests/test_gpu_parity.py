@@ -104,6 +104,7 @@ def test_polar_fio_ragged_parity():
     _check_both(F, bf, n * n, n * n, 2, "c128")
 
 
+@pytest.mark.timeout(900)  # the FP64 oracle builds two coronas at n=64 (about a minute of CPU)
 def test_multiscale_fio_parity():
     mbf = _mbf()
     n = 64
