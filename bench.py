@@ -81,6 +81,19 @@ def roofline(recs, steps, prec):
             "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
 
 
+def hbm_roofline(recs):
+    """Stage launches measured against HBM bandwidth (few right-hand sides)."""
+    stage = [r for r in recs if r["kind"] == 1]
+    st_ms = sum(r["ms"] for r in stage)
+    st_bytes = sum(r["bytes"] for r in stage)
+    achieved = st_bytes / (st_ms * 1e-3) / 1e9 if st_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "stage block product (narrow)",
+            "launches": len(stage), "avg_launch_ms": round(st_ms / max(len(stage), 1), 4),
+            "alg_bytes_per_launch_avg": st_bytes / max(len(stage), 1),
+            "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
+
+
 def measured_traffic(workload, prec):
     """HBM bytes per stage launch from the committed rocprofv3 counter runs
     (profiles/hbm_traffic_*.json), or None when those counters were taken
@@ -188,6 +201,36 @@ def main():
     out["roofline"]["traffic"] = measured_traffic(out["config"]["workload"], "c64")
 
     u32 = u.clone()
+    # few right-hand sides: the streaming (narrow) stage kernel, bound by HBM
+    nn = 16
+    g_n, u_n = g[:, :nn], torch.empty((nn, N), dtype=torch.complex64, device=dev).t()
+    n_total, n_recs = timed_apply(F, g_n, u_n, ws, "c64", args.steps, args.warmup)
+    out["narrow_rhs16"] = {"value": round(nn * args.steps / n_total, 2), "unit": "RHS/s",
+                           "ms_per_step": round(1e3 * n_total / args.steps, 4), "nrhs": nn,
+                           "roofline": hbm_roofline(n_recs)}
+    log("FP32 at %d RHS: %.1f RHS/s" % (nn, out["narrow_rhs16"]["value"]))
+
+    # host-resident inputs and outputs: pinned buffers, copies on the same stream (context, not `value`)
+    g_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
+    u_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
+    g_h.copy_(g.t())
+    g_d = torch.empty((nrhs, N), dtype=torch.complex64, device=dev)
+    u_d = torch.empty((nrhs, N), dtype=torch.complex64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pcie_steps = max(2, args.steps // 2)
+    for _ in range(pcie_steps):
+        g_d.copy_(g_h, non_blocking=True)
+        F.apply(g_d.t(), out=u_d.t(), prec="c64", workspace=ws)
+        u_h.copy_(u_d, non_blocking=True)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    out["pcie_inclusive"] = {"value": round(nrhs * pcie_steps / t_p, 2), "unit": "RHS/s",
+                             "ms_per_step": round(1e3 * t_p / pcie_steps, 4),
+                             "note": "g copied host->device and u device->host (pinned) around each apply"}
+    log("FP32 with host transfers: %.1f RHS/s" % out["pcie_inclusive"]["value"])
+    del g_h, u_h, g_d, u_d
+
     if not args.no_split:
         u16 = torch.empty_like(u)
         s_total, s_recs = timed_apply(F, g, u16, ws, "bf16x3", args.steps, args.warmup)
@@ -206,6 +249,9 @@ def main():
         torch.cuda.synchronize()
         nrm = u64.abs().pow(2).sum().sqrt()
         out["rel_err_vs_fp64_apply"] = float((u32.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
+        u64n = u64[:, :nn]
+        out["narrow_rhs16"]["rel_err_vs_fp64_apply"] = float(
+            (u_n.to(torch.complex128) - u64n).abs().pow(2).sum().sqrt() / u64n.abs().pow(2).sum().sqrt())
         if "split_bf16x3" in out:
             u16 = F.apply(g, prec="bf16x3")
             torch.cuda.synchronize()

@@ -93,6 +93,11 @@ def test_dft_n64_correctness_config():
     g = W.rhs(n * n, 1, seed=0)
     assert direct.rel_err(u, direct.dft_fft(n, g)) < 1e-7
     _check_both(F, bf, n * n, n * n, 64, "c64")
+    # few right-hand sides run the streaming FP32 stage kernel (passes of 8,
+    # 16 or 32 columns); the blocks here have up to 4 x 248 rows, i.e. several
+    # 256-row workgroups per block, with a ragged last one
+    for nrhs in (1, 17, 31):
+        _check_both(F, bf, n * n, n * n, nrhs, "c64", seed=nrhs)
 
 
 def test_polar_fio_ragged_parity():
