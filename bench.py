@@ -31,6 +31,13 @@ CONFIGS = {
     "dft512": dict(kernel="dft", n=512, tol=1e-6, leaf=4, nrhs=256, split="none"),
     "dft256": dict(kernel="dft", n=256, tol=1e-6, leaf=4, nrhs=256, split="none"),
     "dft128": dict(kernel="dft", n=128, tol=1e-6, leaf=4, nrhs=256, split="none"),
+    # FIO of Example 1 with the polar split (Section 3.2), 64 RHS
+    "fio128polar": dict(kernel="fio", n=128, tol=1e-6, leaf=4, nrhs=64, split="polar"),
+    # FIO with the multiscale split (Section 4.2), 16 RHS, apply and adjoint; the
+    # 1024^2 case keeps only the FP32 factors resident
+    "fio256ms": dict(kernel="fio", n=256, tol=1e-4, leaf=4, nrhs=16, split="multiscale", adjoint=True),
+    "fio1024ms": dict(kernel="fio", n=1024, tol=1e-4, leaf=4, nrhs=16, split="multiscale", adjoint=True,
+                      fp32_only=True),
 }
 DEFAULT_CONFIG = os.environ.get("MBF_BENCH_CONFIG", "dft512")
 
@@ -41,22 +48,31 @@ PEAK = {  # MI355X published dense peaks (TFLOP/s)
 }
 
 
+def workload_name(cfg):
+    if cfg["kernel"] == "dft" and cfg["split"] == "none":
+        return "dft2d_n%d_tol%g_leaf%dx%d_rhs%d" % (cfg["n"], cfg["tol"], cfg["leaf"], cfg["leaf"], cfg["nrhs"])
+    return "%s2d_n%d_%s_tol%g_leaf%dx%d_rhs%d" % (cfg["kernel"], cfg["n"], cfg["split"], cfg["tol"], cfg["leaf"],
+                                                 cfg["leaf"], cfg["nrhs"])
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def timed_apply(F, g, u, ws, prec, steps, warmup):
-    """Warmup, then `steps` timed applies bracketed by device synchronisation."""
+def timed_apply(F, g, u, ws, prec, steps, warmup, adjoint=False):
+    """Warmup, then `steps` timed applies (or adjoint applies) bracketed by
+    device synchronisation."""
     import torch
+    fn = F.apply_adjoint if adjoint else F.apply
     for _ in range(warmup):
-        F.apply(g, out=u, prec=prec, workspace=ws)
+        fn(g, out=u, prec=prec, workspace=ws)
     torch.cuda.synchronize()
     inf = F.info()
     F.profile_begin(steps * (4 + 2 * max(inf.depth, 8)) + 64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        F.apply(g, out=u, prec=prec, workspace=ws)
+        fn(g, out=u, prec=prec, workspace=ws)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return t1 - t0, F.profile_end()
@@ -79,6 +95,16 @@ def roofline(recs, steps, prec):
             "alg_bytes_per_step": st_bytes / steps,
             "alg_hbm_gbps": round(st_bytes / (st_ms * 1e-3) / 1e9, 1) if st_ms > 0 else 0.0,
             "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
+
+
+def breakdown(recs, steps):
+    """Milliseconds per step by launch kind (HIP events)."""
+    names = {0: "leaf_project", 1: "stages", 2: "leaf_reconstruct", 3: "center"}
+    out = {}
+    for r in recs:
+        k = names.get(r["kind"], str(r["kind"]))
+        out[k] = out.get(k, 0.0) + r["ms"] / steps
+    return {k: round(v, 4) for k, v in out.items()}
 
 
 def hbm_roofline(recs):
@@ -152,6 +178,8 @@ def main():
     N = n * n
     dev = torch.device("cuda:0")
     x, xi = (W.grid_x_integer(n), W.grid_omega(n)) if cfg["kernel"] == "dft" else (W.grid_x_unit(n), W.grid_omega(n))
+    if cfg.get("fp32_only"):
+        args.no_split = args.no_fp64_check = True
     precs = ["c64"] + ([] if args.no_split else ["bf16x3"])
     t0 = time.time()
     if args.load:
@@ -192,23 +220,35 @@ def main():
     out = {"metric": METRIC, "value": round(value, 2), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "dft2d_n%d_tol%g_leaf%dx%d_rhs%d" % (n, cfg["tol"], cfg["leaf"], cfg["leaf"], nrhs),
-                      "kernel": cfg["kernel"], "n": n, "N": N, "nrhs": nrhs, "tol": cfg["tol"],
+           "config": {"workload": workload_name(cfg),
+                      "kernel": cfg["kernel"], "split": cfg["split"], "n": n, "N": N, "nrhs": nrhs, "tol": cfg["tol"],
                       "depth": inf.depth, "ranks": list(inf.max_rank[:inf.depth + 1]), "nnz": inf.nnz,
                       "factor_gb_on_device": round(inf.device_bytes / 1e9, 3),
                       "setup_s": round(setup_s, 1), "setup": "load" if args.load else "mbf_build (host FP64)"},
-           "roofline": roofline(recs, args.steps, "c64")}
+           "roofline": roofline(recs, args.steps, "c64") if nrhs >= 32 else hbm_roofline(recs)}
     out["roofline"]["traffic"] = measured_traffic(out["config"]["workload"], "c64")
+    out["ms_per_step_by_kind"] = breakdown(recs, args.steps)
 
     u32 = u.clone()
+    if cfg.get("adjoint"):
+        h = torch.empty((nrhs, N), dtype=torch.complex64, device=dev).t()
+        h.copy_(g)
+        v = torch.empty((nrhs, N), dtype=torch.complex64, device=dev).t()
+        a_total, a_recs = timed_apply(F, h, v, ws, "c64", args.steps, args.warmup, adjoint=True)
+        out["adjoint"] = {"value": round(nrhs * args.steps / a_total, 2), "unit": "RHS/s",
+                          "ms_per_step": round(1e3 * a_total / args.steps, 4),
+                          "roofline": roofline(a_recs, args.steps, "c64") if nrhs >= 32 else hbm_roofline(a_recs)}
+        log("FP32 adjoint: %.1f RHS/s" % out["adjoint"]["value"])
+        del h, v
     # few right-hand sides: the streaming (narrow) stage kernel, bound by HBM
     nn = 16
-    g_n, u_n = g[:, :nn], torch.empty((nn, N), dtype=torch.complex64, device=dev).t()
-    n_total, n_recs = timed_apply(F, g_n, u_n, ws, "c64", args.steps, args.warmup)
-    out["narrow_rhs16"] = {"value": round(nn * args.steps / n_total, 2), "unit": "RHS/s",
-                           "ms_per_step": round(1e3 * n_total / args.steps, 4), "nrhs": nn,
-                           "roofline": hbm_roofline(n_recs)}
-    log("FP32 at %d RHS: %.1f RHS/s" % (nn, out["narrow_rhs16"]["value"]))
+    if nrhs > nn:
+        g_n, u_n = g[:, :nn], torch.empty((nn, N), dtype=torch.complex64, device=dev).t()
+        n_total, n_recs = timed_apply(F, g_n, u_n, ws, "c64", args.steps, args.warmup)
+        out["narrow_rhs16"] = {"value": round(nn * args.steps / n_total, 2), "unit": "RHS/s",
+                               "ms_per_step": round(1e3 * n_total / args.steps, 4), "nrhs": nn,
+                               "roofline": hbm_roofline(n_recs)}
+        log("FP32 at %d RHS: %.1f RHS/s" % (nn, out["narrow_rhs16"]["value"]))
 
     # host-resident inputs and outputs: pinned buffers, copies on the same stream (context, not `value`)
     g_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
@@ -249,9 +289,10 @@ def main():
         torch.cuda.synchronize()
         nrm = u64.abs().pow(2).sum().sqrt()
         out["rel_err_vs_fp64_apply"] = float((u32.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
-        u64n = u64[:, :nn]
-        out["narrow_rhs16"]["rel_err_vs_fp64_apply"] = float(
-            (u_n.to(torch.complex128) - u64n).abs().pow(2).sum().sqrt() / u64n.abs().pow(2).sum().sqrt())
+        if "narrow_rhs16" in out:
+            u64n = u64[:, :nn]
+            out["narrow_rhs16"]["rel_err_vs_fp64_apply"] = float(
+                (u_n.to(torch.complex128) - u64n).abs().pow(2).sum().sqrt() / u64n.abs().pow(2).sum().sqrt())
         if "split_bf16x3" in out:
             u16 = F.apply(g, prec="bf16x3")
             torch.cuda.synchronize()

@@ -269,6 +269,120 @@ __global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __rest
   }
 }
 
+// Small leaves (at most 16 points and rank 16, e.g. 4 x 4 leaves): one
+// workgroup per leaf and 64 right-hand sides; thread (t % 16, t / 16) owns
+// output row t % 16 for the right-hand sides t / 16 + 16 j.  The stores of 16
+// consecutive lanes cover 16 consecutive state rows (projection) or the
+// leaf's gathered points (reconstruction).
+constexpr int kSmallLeaf = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_project_small(const LeafDesc* __restrict__ leaves,
+                                                            const typename cx<T>::t* __restrict__ F,
+                                                            const int32_t* __restrict__ idx,
+                                                            const typename cx<T>::t* __restrict__ x,
+                                                            int64_t ldx, typename cx<T>::t* __restrict__ out,
+                                                            int64_t ld_out, int nrhs,
+                                                            const T* __restrict__ scale) {
+  using C = typename cx<T>::t;
+  __shared__ C Xs[kSmallLeaf][65];
+  __shared__ C Fs[kSmallLeaf][kSmallLeaf + 1];
+  const LeafDesc d = leaves[blockIdx.x];
+  const int n0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  const C* Fb = F + d.f_off;
+  for (int e = tid; e < kSmallLeaf * 64; e += 256) {
+    const int i = e & 15, n = e >> 4;
+    C v = czero<C>();
+    if (i < d.np && n0 + n < nrhs) v = x[(int64_t)(n0 + n) * ldx + idx[d.p_off + i]];
+    Xs[i][n] = v;
+  }
+  {
+    const int i = tid & 15, k = tid >> 4;
+    C v = czero<C>();
+    if (i < d.np && k < d.r) v = cconj(Fb[(int64_t)k * d.np + i]);
+    Fs[i][k] = v;
+  }
+  __syncthreads();
+  const int tk = tid & 15, tn = tid >> 4;
+  C acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = czero<C>();
+  for (int i = 0; i < d.np; ++i) {
+    const C f = Fs[i][tk];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cfma(acc[j], f, Xs[i][tn + 16 * j]);
+  }
+  if (tk < d.r) {
+    const int32_t row = d.row + tk;
+    const T s = scale ? scale[row] : T(1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tn + 16 * j;
+      if (n < nrhs) {
+        C v = acc[j];
+        v.x *= s;
+        v.y *= s;
+        out[(int64_t)n * ld_out + row] = v;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_reconstruct_small(const LeafDesc* __restrict__ leaves,
+                                                                const typename cx<T>::t* __restrict__ F,
+                                                                const int32_t* __restrict__ idx,
+                                                                const typename cx<T>::t* __restrict__ z,
+                                                                int64_t ldz, typename cx<T>::t* __restrict__ x,
+                                                                int64_t ldx, int nrhs, int accumulate) {
+  using C = typename cx<T>::t;
+  __shared__ C Zs[kSmallLeaf][65];
+  __shared__ C Fs[kSmallLeaf][kSmallLeaf + 1];
+  const LeafDesc d = leaves[blockIdx.x];
+  const int n0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  const C* Fb = F + d.f_off;
+  for (int e = tid; e < kSmallLeaf * 64; e += 256) {
+    const int k = e & 15, n = e >> 4;
+    C v = czero<C>();
+    if (k < d.r && n0 + n < nrhs) v = z[(int64_t)(n0 + n) * ldz + d.row + k];
+    Zs[k][n] = v;
+  }
+  {
+    const int i = tid & 15, k = tid >> 4;
+    C v = czero<C>();
+    if (i < d.np && k < d.r) v = Fb[(int64_t)k * d.np + i];
+    Fs[i][k] = v;
+  }
+  __syncthreads();
+  const int ti = tid & 15, tn = tid >> 4;
+  if (ti >= d.np) return;
+  C acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = czero<C>();
+  for (int k = 0; k < d.r; ++k) {
+    const C f = Fs[ti][k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cfma(acc[j], f, Zs[k][tn + 16 * j]);
+  }
+  const int64_t p = idx[d.p_off + ti];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + tn + 16 * j;
+    if (n < nrhs) {
+      C v = acc[j];
+      C* o = x + (int64_t)n * ldx + p;
+      if (accumulate) {
+        const C w = *o;
+        v.x += w.x;
+        v.y += w.y;
+      }
+      *o = v;
+    }
+  }
+}
+
 // u[i, n] (+)= sum_k KC[i + k nx] g[cidx[k], n]     (dense center, forward)
 template <typename T>
 __global__ __launch_bounds__(256) void k_center_fwd(const typename cx<T>::t* __restrict__ KC,
@@ -438,11 +552,31 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   };
   const C* Vf = reinterpret_cast<const C*>(pd.V0);
   const C* Uf = reinterpret_cast<const C*>(pd.UL);
+  const bool v_small = P.max_vnp <= kSmallLeaf && P.max_vr <= kSmallLeaf;
+  const bool u_small = P.max_unp <= kSmallLeaf && P.max_ur <= kSmallLeaf;
+  const unsigned nt64 = (unsigned)((nrhs + 63) / 64);
+  auto project = [&](bool small, int32_t nleaf, const LeafDesc* lv, const C* Fl, const int32_t* idx, C* dst,
+                     int64_t lddst, const T* sc) {
+    if (small)
+      hipLaunchKernelGGL(k_leaf_project_small<T>, dim3(nleaf, nt64), dim3(256), 0, st, lv, Fl, idx,
+                         reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
+    else
+      hipLaunchKernelGGL(k_leaf_project<T>, dim3(nleaf, nt), dim3(256), 0, st, lv, Fl, idx,
+                         reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
+  };
+  auto reconstruct = [&](bool small, int32_t nleaf, const LeafDesc* lv, const C* Fl, const int32_t* idx,
+                         const C* src, int64_t ldsrc, int acc) {
+    if (small)
+      hipLaunchKernelGGL(k_leaf_reconstruct_small<T>, dim3(nleaf, nt64), dim3(256), 0, st, lv, Fl, idx, src, ldsrc,
+                         reinterpret_cast<C*>(out), ldout, ni, acc);
+    else
+      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(nleaf, nt), dim3(256), 0, st, lv, Fl, idx, src, ldsrc,
+                         reinterpret_cast<C*>(out), ldout, ni, acc);
+  };
   if (!adj) {
     if (P.n_vleaf > 0) {
       Timed t(pr, st, 0, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
-      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf, Vf, P.d_vidx,
-                         reinterpret_cast<const C*>(in), ldin, buf[0], P.ld[0], ni, m == 0 ? S : nullptr);
+      project(v_small, P.n_vleaf, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], m == 0 ? S : nullptr);
     }
     for (int s = 0; s < L; ++s) {
       if (P.nblk[s] == 0) continue;
@@ -466,14 +600,12 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
     }
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 2, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
-      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf, Uf, P.d_uidx,
-                         buf[L & 1], P.ld[L], reinterpret_cast<C*>(out), ldout, ni, accumulate ? 1 : 0);
+      reconstruct(u_small, P.n_uleaf, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L], accumulate ? 1 : 0);
     }
   } else {
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 0, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
-      hipLaunchKernelGGL(k_leaf_project<T>, dim3(P.n_uleaf, nt), dim3(256), 0, st, P.d_uleaf, Uf, P.d_uidx,
-                         reinterpret_cast<const C*>(in), ldin, buf[L & 1], P.ld[L], ni, m == L ? S : nullptr);
+      project(u_small, P.n_uleaf, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L], m == L ? S : nullptr);
     }
     for (int s = L - 1; s >= 0; --s) {
       if (P.nblk[s] == 0) continue;
@@ -497,8 +629,7 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
     }
     if (P.n_vleaf > 0) {
       Timed t(pr, st, 2, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
-      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(P.n_vleaf, nt), dim3(256), 0, st, P.d_vleaf, Vf, P.d_vidx,
-                         buf[0], P.ld[0], reinterpret_cast<C*>(out), ldout, ni, 0);
+      reconstruct(v_small, P.n_vleaf, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], 0);
     }
   }
   return hip_check("apply launch");
