@@ -237,7 +237,8 @@ def main():
         a_total, a_recs = timed_apply(F, h, v, ws, "c64", args.steps, args.warmup, adjoint=True)
         out["adjoint"] = {"value": round(nrhs * args.steps / a_total, 2), "unit": "RHS/s",
                           "ms_per_step": round(1e3 * a_total / args.steps, 4),
-                          "roofline": roofline(a_recs, args.steps, "c64") if nrhs >= 32 else hbm_roofline(a_recs)}
+                          "roofline": roofline(a_recs, args.steps, "c64") if nrhs >= 32 else hbm_roofline(a_recs),
+                          "ms_per_step_by_kind": breakdown(a_recs, args.steps)}
         log("FP32 adjoint: %.1f RHS/s" % out["adjoint"]["value"])
         del h, v
     # few right-hand sides: the streaming (narrow) stage kernel, bound by HBM

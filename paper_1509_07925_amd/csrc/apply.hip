@@ -213,6 +213,10 @@ __global__ __launch_bounds__(256) void k_leaf_project(const LeafDesc* __restrict
 }
 
 // x[idx[p_off + i], n] (+)= sum_k F[i + k np] z[row + k, n]
+// One workgroup per (leaf, chunk of 64 points, 32 right-hand sides): the rows
+// of a leaf are independent, so large leaves (the coarse coronas of the
+// multiscale split have leaves of thousands of points) spread over many
+// workgroups.
 template <typename T>
 __global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __restrict__ leaves,
                                                           const typename cx<T>::t* __restrict__ F,
@@ -223,47 +227,47 @@ __global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __rest
   using C = typename cx<T>::t;
   __shared__ C Zs[64][33];
   const LeafDesc d = leaves[blockIdx.x];
-  const int n0 = blockIdx.y * 32;
+  const int i0 = blockIdx.y * 64;
+  if (i0 >= d.np) return;
+  const int n0 = blockIdx.z * 32;
   const int tid = threadIdx.x;
   const int ti = tid & 63, tn = tid >> 6;
   const C* Fb = F + d.f_off;
-  for (int i0 = 0; i0 < d.np; i0 += 64) {
-    C acc[8];
+  C acc[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
-    for (int k0 = 0; k0 < d.r; k0 += 64) {
-      for (int e = tid; e < 64 * 32; e += 256) {
-        const int k = e & 63, n = e >> 6;
-        C v = czero<C>();
-        if (k0 + k < d.r && n0 + n < nrhs) v = z[(int64_t)(n0 + n) * ldz + d.row + k0 + k];
-        Zs[k][n] = v;
-      }
-      __syncthreads();
-      if (i0 + ti < d.np) {
-        const int klim = min(64, d.r - k0);
-        for (int k = 0; k < klim; ++k) {
-          const C f = Fb[(int64_t)(k0 + k) * d.np + i0 + ti];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) cfma(acc[j], f, Zs[k][tn + 4 * j]);
-        }
-      }
-      __syncthreads();
+  for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
+  for (int k0 = 0; k0 < d.r; k0 += 64) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int k = e & 63, n = e >> 6;
+      C v = czero<C>();
+      if (k0 + k < d.r && n0 + n < nrhs) v = z[(int64_t)(n0 + n) * ldz + d.row + k0 + k];
+      Zs[k][n] = v;
     }
+    __syncthreads();
     if (i0 + ti < d.np) {
-      const int64_t p = idx[d.p_off + i0 + ti];
+      const int klim = min(64, d.r - k0);
+      for (int k = 0; k < klim; ++k) {
+        const C f = Fb[(int64_t)(k0 + k) * d.np + i0 + ti];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int n = n0 + tn + 4 * j;
-        if (n < nrhs) {
-          C v = acc[j];
-          C* o = x + (int64_t)n * ldx + p;
-          if (accumulate) {
-            C w = *o;
-            v.x += w.x;
-            v.y += w.y;
-          }
-          *o = v;
+        for (int j = 0; j < 8; ++j) cfma(acc[j], f, Zs[k][tn + 4 * j]);
+      }
+    }
+    __syncthreads();
+  }
+  if (i0 + ti < d.np) {
+    const int64_t p = idx[d.p_off + i0 + ti];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = n0 + tn + 4 * j;
+      if (n < nrhs) {
+        C v = acc[j];
+        C* o = x + (int64_t)n * ldx + p;
+        if (accumulate) {
+          C w = *o;
+          v.x += w.x;
+          v.y += w.y;
         }
+        *o = v;
       }
     }
   }
@@ -564,14 +568,14 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       hipLaunchKernelGGL(k_leaf_project<T>, dim3(nleaf, nt), dim3(256), 0, st, lv, Fl, idx,
                          reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
   };
-  auto reconstruct = [&](bool small, int32_t nleaf, const LeafDesc* lv, const C* Fl, const int32_t* idx,
-                         const C* src, int64_t ldsrc, int acc) {
+  auto reconstruct = [&](bool small, int32_t nleaf, int32_t max_np, const LeafDesc* lv, const C* Fl,
+                         const int32_t* idx, const C* src, int64_t ldsrc, int acc) {
     if (small)
       hipLaunchKernelGGL(k_leaf_reconstruct_small<T>, dim3(nleaf, nt64), dim3(256), 0, st, lv, Fl, idx, src, ldsrc,
                          reinterpret_cast<C*>(out), ldout, ni, acc);
     else
-      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(nleaf, nt), dim3(256), 0, st, lv, Fl, idx, src, ldsrc,
-                         reinterpret_cast<C*>(out), ldout, ni, acc);
+      hipLaunchKernelGGL(k_leaf_reconstruct<T>, dim3(nleaf, (unsigned)((max_np + 63) / 64), nt), dim3(256), 0, st,
+                         lv, Fl, idx, src, ldsrc, reinterpret_cast<C*>(out), ldout, ni, acc);
   };
   if (!adj) {
     if (P.n_vleaf > 0) {
@@ -600,7 +604,7 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
     }
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 2, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
-      reconstruct(u_small, P.n_uleaf, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L], accumulate ? 1 : 0);
+      reconstruct(u_small, P.n_uleaf, P.max_unp, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L], accumulate ? 1 : 0);
     }
   } else {
     if (P.n_uleaf > 0) {
@@ -629,7 +633,7 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
     }
     if (P.n_vleaf > 0) {
       Timed t(pr, st, 2, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
-      reconstruct(v_small, P.n_vleaf, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], 0);
+      reconstruct(v_small, P.n_vleaf, P.max_vnp, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], 0);
     }
   }
   return hip_check("apply launch");
