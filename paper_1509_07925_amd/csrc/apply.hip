@@ -273,6 +273,59 @@ __global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __rest
   }
 }
 
+// Projection onto leaves with many points (the coarse coronas of the
+// multiscale split): one wave per (leaf, output row k, 16 right-hand sides);
+// the lanes stride over the leaf's points and the sums are combined across
+// the wave with shuffles, so a leaf of thousands of points spreads over r
+// waves instead of one workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_project_wide(const LeafDesc* __restrict__ leaves,
+                                                           const typename cx<T>::t* __restrict__ F,
+                                                           const int32_t* __restrict__ idx,
+                                                           const typename cx<T>::t* __restrict__ x,
+                                                           int64_t ldx, typename cx<T>::t* __restrict__ out,
+                                                           int64_t ld_out, int nrhs,
+                                                           const T* __restrict__ scale) {
+  using C = typename cx<T>::t;
+  constexpr int NRW = 16;
+  const LeafDesc d = leaves[blockIdx.x];
+  const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (k >= d.r) return;  // whole wave; no workgroup barrier below
+  const int lane = threadIdx.x & 63;
+  const int n0 = blockIdx.z * NRW;
+  const int nn = min(NRW, nrhs - n0);
+  const C* Fk = F + d.f_off + (int64_t)k * d.np;
+  C acc[NRW];
+#pragma unroll
+  for (int n = 0; n < NRW; ++n) acc[n] = czero<C>();
+  for (int i = lane; i < d.np; i += 64) {
+    const C f = cconj(Fk[i]);
+    const int64_t p = idx[d.p_off + i];
+#pragma unroll
+    for (int n = 0; n < NRW; ++n)
+      if (n < nn) cfma(acc[n], f, x[(int64_t)(n0 + n) * ldx + p]);
+  }
+#pragma unroll
+  for (int n = 0; n < NRW; ++n)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc[n].x += __shfl_xor(acc[n].x, off);
+      acc[n].y += __shfl_xor(acc[n].y, off);
+    }
+  if (lane == 0) {
+    const int32_t row = d.row + k;
+    const T s = scale ? scale[row] : T(1);
+#pragma unroll
+    for (int n = 0; n < NRW; ++n)
+      if (n < nn) {
+        C v = acc[n];
+        v.x *= s;
+        v.y *= s;
+        out[(int64_t)(n0 + n) * ld_out + row] = v;
+      }
+  }
+}
+
 // Small leaves (at most 16 points and rank 16, e.g. 4 x 4 leaves): one
 // workgroup per leaf and 64 right-hand sides; thread (t % 16, t / 16) owns
 // output row t % 16 for the right-hand sides t / 16 + 16 j.  The stores of 16
@@ -559,9 +612,12 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   const bool v_small = P.max_vnp <= kSmallLeaf && P.max_vr <= kSmallLeaf;
   const bool u_small = P.max_unp <= kSmallLeaf && P.max_ur <= kSmallLeaf;
   const unsigned nt64 = (unsigned)((nrhs + 63) / 64);
-  auto project = [&](bool small, int32_t nleaf, const LeafDesc* lv, const C* Fl, const int32_t* idx, C* dst,
-                     int64_t lddst, const T* sc) {
-    if (small)
+  auto project = [&](bool small, int32_t nleaf, int32_t max_np, int32_t max_r, const LeafDesc* lv, const C* Fl,
+                     const int32_t* idx, C* dst, int64_t lddst, const T* sc) {
+    if (!small && max_np > 256)
+      hipLaunchKernelGGL(k_leaf_project_wide<T>, dim3(nleaf, (unsigned)((max_r + 3) / 4), (unsigned)((nrhs + 15) / 16)),
+                         dim3(256), 0, st, lv, Fl, idx, reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
+    else if (small)
       hipLaunchKernelGGL(k_leaf_project_small<T>, dim3(nleaf, nt64), dim3(256), 0, st, lv, Fl, idx,
                          reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
     else
@@ -580,7 +636,7 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   if (!adj) {
     if (P.n_vleaf > 0) {
       Timed t(pr, st, 0, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
-      project(v_small, P.n_vleaf, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], m == 0 ? S : nullptr);
+      project(v_small, P.n_vleaf, P.max_vnp, P.max_vr, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], m == 0 ? S : nullptr);
     }
     for (int s = 0; s < L; ++s) {
       if (P.nblk[s] == 0) continue;
@@ -609,7 +665,8 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   } else {
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 0, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
-      project(u_small, P.n_uleaf, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L], m == L ? S : nullptr);
+      project(u_small, P.n_uleaf, P.max_unp, P.max_ur, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L],
+              m == L ? S : nullptr);
     }
     for (int s = L - 1; s >= 0; --s) {
       if (P.nblk[s] == 0) continue;

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(NT) void k_stage_narrow(const BlockDesc* __restrict
 #pragma unroll
   for (int n = 0; n < NR; ++n) acc[n] = make_float2(0.f, 0.f);
   for (int q0 = 0; q0 < Q; q0 += KCN) {
-    float2 w[KCN];
+    float2 w[ADJ ? 1 : KCN];
     if (!ADJ) {  // issue the chunk's W loads first; they land while x is staged
 #pragma unroll
       for (int k = 0; k < KCN; ++k) {
@@ -60,12 +60,20 @@ __global__ __launch_bounds__(NT) void k_stage_narrow(const BlockDesc* __restrict
         if (r < R && q0 + k < Q) v = Wb[(int64_t)(q0 + k) * d.M + r];
         w[k] = v;
       }
-    } else {
-      for (int e = tid; e < NT * KCN; e += NT) {
-        const int mm = e % KCN, ko = e / KCN;
-        float2 v = make_float2(0.f, 0.f);
-        if (r0 + ko < R && q0 + mm < Q) v = Wb[(int64_t)(r0 + ko) * d.M + q0 + mm];
-        Ws[ko][mm] = v;
+    } else {  // two rounds of 16 loads in flight before their LDS stores
+      const int mm = tid % KCN;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float2 t[KCN / 2];
+#pragma unroll
+        for (int j = 0; j < KCN / 2; ++j) {
+          const int ko = tid / KCN + (h * (KCN / 2) + j) * (NT / KCN);
+          float2 v = make_float2(0.f, 0.f);
+          if (r0 + ko < R && q0 + mm < Q) v = Wb[(int64_t)(r0 + ko) * d.M + q0 + mm];
+          t[j] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < KCN / 2; ++j) Ws[tid / KCN + (h * (KCN / 2) + j) * (NT / KCN)][mm] = t[j];
       }
     }
     for (int e = tid; e < KCN * NR; e += NT) {  // lanes along k: consecutive state rows
@@ -76,16 +84,13 @@ __global__ __launch_bounds__(NT) void k_stage_narrow(const BlockDesc* __restrict
       Xs[k][n] = v;
     }
     __syncthreads();
-    if (ADJ) {
-#pragma unroll
-      for (int k = 0; k < KCN; ++k) w[k] = Ws[tid][k];
-    }
     float2 p[NR];
 #pragma unroll
     for (int n = 0; n < NR; ++n) p[n] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < KCN; ++k) {
-      const float wr = w[k].x, wi = ADJ ? -w[k].y : w[k].y;
+      const float2 wk = ADJ ? Ws[tid][k] : w[k];
+      const float wr = wk.x, wi = ADJ ? -wk.y : wk.y;
 #pragma unroll
       for (int n = 0; n < NR; ++n) {
         const float2 xv = Xs[k][n];
