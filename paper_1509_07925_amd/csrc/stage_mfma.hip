@@ -284,15 +284,23 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
         const int col = wm + 32 * c + li;
         bv[c] = *reinterpret_cast<const float4*>(&Bs[buf][kk][bidx_pad(col >> 1, col & 1, kb >> 2)]);
       }
+      // consecutive instructions go to different accumulator tiles
 #pragma unroll
       for (int a = 0; a < RT; ++a)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[c].x, p[a][c], 0, 0, 0);
-          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, bv[c].y, p[a][c], 0, 0, 0);
-          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].z, bv[c].z, p[a][c], 0, 0, 0);
-          p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].w, bv[c].w, p[a][c], 0, 0, 0);
-        }
+        for (int c = 0; c < CT; ++c) p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].x, bv[c].x, p[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].y, bv[c].y, p[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].z, bv[c].z, p[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) p[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a].w, bv[c].w, p[a][c], 0, 0, 0);
     }
 #pragma unroll
     for (int a = 0; a < RT; ++a)
@@ -417,14 +425,19 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
         bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[buf][e]));
         bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[buf][e]));
       }
+      // consecutive instructions go to different accumulator tiles
 #pragma unroll
       for (int a = 0; a < RT; ++a)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
-          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
-          acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
-        }
+        for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
     }
   };
   if (S::DB) {
