@@ -335,6 +335,168 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
   store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
+// ------------------------------------------------------------------ FP32, 3 real products
+// The complex product as three real products (Gauss): with X = Xr + i Xi
+// and B = Br + i Bi,
+//   T1 = Xr Br,  T2 = Xi Bi,  T3 = (Xr + Xi)(Br + Bi),
+//   Re = T1 - T2,  Im = T3 - T1 - T2,
+// i.e. 6 real flops of matrix-core work per complex multiply-add instead of
+// the 8 of the real embedding.  Each MFMA consumes two complex k (lanes 0-31
+// k, lanes 32-63 k + 4 of a group of 8).  The wave tile is 32 RT right-hand
+// sides x 32 CT complex output rows; T1..T3 are summed in two levels like the
+// other FP32 kernels.
+template <int TNV_, int TMV_, int NTH_, int RT_, int CT_, bool PF_, bool DB_>
+struct Shape3 {
+  static constexpr int TNV = TNV_, TMV = TMV_, NTH = NTH_, RT = RT_, CT = CT_;
+  static constexpr bool PF = PF_ || DB_, DB = DB_;
+  static constexpr int WR = TNV / (32 * RT);  // waves along right-hand sides
+  static constexpr int WC = TMV / (32 * CT);  // waves along complex output rows
+  static_assert(WR * WC * 64 == NTH, "the waves must cover the tile");
+  static constexpr int EA = TNV * KCH / NTH;
+  static constexpr int EB = TMV * 4 / NTH;
+  static_assert(EA * NTH == TNV * KCH && EB * NTH == TMV * 4 && NTH % KCH == 0, "load mapping");
+  static constexpr int NB = DB ? 2 : 1;
+};
+
+template <bool ADJ, class S>
+__global__ __launch_bounds__(S::NTH) void k_stage_f32_3m(const BlockDesc* __restrict__ blk,
+                                                         const float2* __restrict__ W,
+                                                         const float2* __restrict__ in, int64_t ld_in,
+                                                         float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                         const float* __restrict__ scale, int mtiles, int ntiles,
+                                                         int64_t total) {
+  constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
+  __shared__ __attribute__((aligned(16))) float As[NB][3][TNV * PA];  // [buf][Xr|Xi|Xr+Xi][n][k]
+  __shared__ __attribute__((aligned(16))) float Bs[NB][3][TMV * PA];  // [buf][Br|Bi|Br+Bi][m][k]
+  const Tile tl = map_tile(total, mtiles, ntiles);
+  if (tl.b < 0) return;
+  const BlockDesc d = blk[tl.b];
+  const int R = ADJ ? d.K : d.M;
+  const int Q = ADJ ? d.M : d.K;
+  const int r0 = tl.mt * TMV;
+  if (r0 >= R) return;
+  const int n0 = tl.nt * TNV;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
+  const float2* Wb = W + d.w_off;
+  using LD = Loader<S, ADJ, float2>;
+  LD ld;
+  auto stash = [&](int buf) {
+    const int k = tid % KCH, n = tid / KCH;
+#pragma unroll
+    for (int j = 0; j < S::EA; ++j) {
+      const int e = (n + j * (NTH / KCH)) * PA + k;
+      const float2 v = ld.a[j];
+      As[buf][0][e] = v.x;
+      As[buf][1][e] = v.y;
+      As[buf][2][e] = v.x + v.y;
+    }
+#pragma unroll
+    for (int j = 0; j < S::EB; ++j) {
+      int mrow, g;
+      LD::pair_pos(j, mrow, g);
+      const float2* w = ld.b[j];
+      const float s = ADJ ? -1.f : 1.f;  // B = W (forward) or conj(W) (adjoint)
+      const int e = mrow * PA + 4 * g;
+      *reinterpret_cast<float4*>(&Bs[buf][0][e]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
+      *reinterpret_cast<float4*>(&Bs[buf][1][e]) = make_float4(s * w[0].y, s * w[1].y, s * w[2].y, s * w[3].y);
+      *reinterpret_cast<float4*>(&Bs[buf][2][e]) =
+          make_float4(w[0].x + s * w[0].y, w[1].x + s * w[1].y, w[2].x + s * w[2].y, w[3].x + s * w[3].y);
+    }
+  };
+  v16f acc[3][RT][CT];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][a][c] = v16f{};
+  const int kk = lane >> 5, li = lane & 31;
+  auto compute = [&](int buf) {
+    v16f p[3][RT][CT];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) p[t][a][c] = v16f{};
+#pragma unroll
+    for (int kb = 0; kb < KCH; kb += 8) {
+      const int ko = kb + 4 * kk;
+      float4 av[3][RT], bv[3][CT];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+          av[t][a] = *reinterpret_cast<const float4*>(&As[buf][t][(wn + 32 * a + li) * PA + ko]);
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          bv[t][c] = *reinterpret_cast<const float4*>(&Bs[buf][t][(wm + 32 * c + li) * PA + ko]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+          for (int a = 0; a < RT; ++a)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+              const float x = j == 0 ? av[t][a].x : j == 1 ? av[t][a].y : j == 2 ? av[t][a].z : av[t][a].w;
+              const float y = j == 0 ? bv[t][c].x : j == 1 ? bv[t][c].y : j == 2 ? bv[t][c].z : bv[t][c].w;
+              p[t][a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, p[t][a][c], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][a][c] += p[t][a][c];
+  };
+  if (S::DB) {
+    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    stash(0);
+    if (KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
+    __syncthreads();
+    for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
+      if (q0 + KCH < Q) {
+        stash(cur ^ 1);
+        if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+      }
+      compute(cur);
+      __syncthreads();
+    }
+  } else {
+    if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    for (int q0 = 0; q0 < Q; q0 += KCH) {
+      if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+      stash(0);
+      __syncthreads();
+      if (S::PF && q0 + KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
+      compute(0);
+      __syncthreads();
+    }
+  }
+  // Re = T1 - T2, Im = T3 - T1 - T2; lane li holds complex row wm + 32 c + li
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int m = r0 + wm + 32 * c + li;
+    if (m >= R) continue;
+    const int32_t row = ADJ ? d.in_row + m : grp_row(d, m);
+    const float sc = scale ? scale[row] : 1.0f;
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int n = n0 + wn + 32 * a + 8 * (j >> 2) + 4 * kk + (j & 3);
+        if (n < nrhs) {
+          const float t1 = acc[0][a][c][j], t2 = acc[1][a][c][j], t3 = acc[2][a][c][j];
+          out[(int64_t)n * ld_out + row] = make_float2((t1 - t2) * sc, (t3 - t1 - t2) * sc);
+        }
+      }
+  }
+}
+
 // ------------------------------------------------------------------ BF16 x3
 // LDS words hold two BF16 values along the reduction: the state word (n, k)
 // is (Re, Im) of x(n, k); the block words are the matching pairs of the
@@ -475,6 +637,10 @@ using F2 = Shape<128, 64, 256, 2, 2, true, false>;
 using F3 = Shape<64, 64, 256, 1, 2, true, true>;
 using F4 = Shape<128, 64, 256, 2, 2, true, true>;
 using F5 = Shape<128, 128, 512, 2, 2, true, true>;
+// FP32 with three real products (k_stage_f32_3m)
+using G6 = Shape3<64, 64, 256, 1, 1, false, false>;
+using G7 = Shape3<64, 64, 256, 1, 1, true, false>;
+using G8 = Shape3<64, 64, 256, 1, 1, true, true>;
 using B0 = Shape<64, 64, 256, 1, 2, false, false>;
 using B1 = Shape<128, 64, 256, 2, 2, true, false>;
 using B2 = Shape<256, 128, 512, 2, 4, true, false>;
@@ -499,7 +665,10 @@ VariantDims variant_dims(int prec, int v) {
       case 2: return dims_of<F2>();
       case 3: return dims_of<F3>();
       case 4: return dims_of<F4>();
-      default: return dims_of<F5>();
+      case 5: return dims_of<F5>();
+      case 6: return dims_of<G6>();
+      case 7: return dims_of<G7>();
+      default: return dims_of<G8>();
     }
   }
   switch (v) {
@@ -580,7 +749,10 @@ static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const Blo
       case 2: MBF_LAUNCH(k_stage_f32, float2, F2); break;
       case 3: MBF_LAUNCH(k_stage_f32, float2, F3); break;
       case 4: MBF_LAUNCH(k_stage_f32, float2, F4); break;
-      default: MBF_LAUNCH(k_stage_f32, float2, F5); break;
+      case 5: MBF_LAUNCH(k_stage_f32, float2, F5); break;
+      case 6: MBF_LAUNCH(k_stage_f32_3m, float2, G6); break;
+      case 7: MBF_LAUNCH(k_stage_f32_3m, float2, G7); break;
+      default: MBF_LAUNCH(k_stage_f32_3m, float2, G8); break;
     }
   } else {
     switch (v) {

@@ -228,7 +228,7 @@ def test_save_load_roundtrip_is_bit_exact(tmp_path):
         _mbf().Factor.load(path)
 
 
-@pytest.mark.parametrize("prec,variant", [("c64", v) for v in range(6)] + [("bf16x3", v) for v in range(7)])
+@pytest.mark.parametrize("prec,variant", [("c64", v) for v in range(9)] + [("bf16x3", v) for v in range(7)])
 def test_every_stage_kernel_variant_is_exact(variant, prec, monkeypatch):
     """The autotuner may pick any variant: all of them must meet the bar.
     300 right-hand sides span several RHS tiles of every width (64, 128, 256)
