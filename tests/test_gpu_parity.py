@@ -248,3 +248,41 @@ def test_autotune_keeps_results_within_bar():
     assert F.autotune("bf16x3", 96) > 0
     _check_both(F, bf, n * n, n * n, 96, "c64", seed=5)
     _check_both(F, bf, n * n, n * n, 96, "bf16x3", seed=6)
+
+
+@pytest.mark.parametrize("prec,bound", [("c128", 1e-12), ("c64", 1e-5)])
+def test_adjoint_identity_on_gpu(prec, bound):
+    """<K g, h> = <g, K^* h> for the factorized operator as applied on the
+    GPU (Section 2.3: the adjoint is the reversed chain of conjugate-
+    transposed factors), with blocks of several workgroups (n = 64, 8 x 8
+    leaves, ranks up to 248)."""
+    n = 64
+    bf = _dft_oracle(n, 8, 1e-8)
+    F = _import(bf, [prec])
+    g = W.rhs(n * n, 3, seed=11)
+    h = W.rhs(n * n, 3, seed=12)
+    Kg = _from_gpu(F.apply(_to_gpu(g, prec), prec=prec))
+    Kh = _from_gpu(F.apply_adjoint(_to_gpu(h, prec), prec=prec))
+    lhs = np.vdot(h, Kg)
+    rhs = np.vdot(Kh, g)
+    assert abs(lhs - rhs) <= bound * np.linalg.norm(Kg) * np.linalg.norm(h)
+
+
+def test_autotune_choices_persist_in_tune_file(tmp_path, monkeypatch):
+    """mbf_autotune appends one line per tuned stage shape to MBF_TUNE_FILE
+    ("prec adj rows-bucket reduction-bucket rhs-bucket variant"), every
+    variant index valid for its precision."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MBF_TUNE_FILE", str(path))
+    n = 32
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, ["c64", "bf16x3"])
+    tuned = F.autotune("c64", 200) + F.autotune("bf16x3", 200)
+    assert tuned > 0
+    lines = [l.split() for l in path.read_text().splitlines() if l.strip()]
+    assert len(lines) == tuned
+    for prec_id, adj, rb, qb, nb, v in (tuple(map(int, l)) for l in lines):
+        assert prec_id in (1, 2) and adj in (0, 1) and rb >= 1 and qb >= 1 and nb >= 1
+        assert 0 <= v < (9 if prec_id == 1 else 7)
+    _check_both(F, bf, n * n, n * n, 200, "c64", seed=3)
+    _check_both(F, bf, n * n, n * n, 200, "bf16x3", seed=4)
