@@ -305,6 +305,10 @@ def main():
 
     if not args.no_serve:
         out["serving"] = serve_mix(F, N, dev)
+        out["serving_multi"] = serve_multi(args.config, F, N, dev)
+        log("served: p50 %.1f ms p99 %.1f ms; %d factorizations: p50 %.1f ms p99 %.1f ms" % (
+            out["serving"]["p50_ms"], out["serving"]["p99_ms"], out["serving_multi"]["factorizations"],
+            out["serving_multi"]["p50_ms"], out["serving_multi"]["p99_ms"]))
 
     u_np = u32.t().contiguous().cpu().numpy().astype(np.complex128).T
     if not args.no_cpu_baseline:
@@ -349,6 +353,81 @@ def serve_mix(F, N, dev, nreq=400, seed=0):
             "rhs_per_s": round(st["rhs"] / st["wall_s"], 1) if st["wall_s"] > 0 else None,
             "offered_rhs_per_s": round(rate * float(np.mean(sizes)), 1),
             "max_concurrent_batches": int(st["max_concurrent_batches"])}
+
+
+# Extra resident factorizations for the multi-factor serving leg: DFT and FIO
+# (polar and multiscale) at uneven sizes, beside the benchmark's own factor.
+SERVE_EXTRA = [
+    ("dft64", dict(kernel="dft", n=64, tol=1e-6, leaf=4, split="none")),
+    ("dft128", dict(kernel="dft", n=128, tol=1e-6, leaf=4, split="none")),
+    ("fio64polar", dict(kernel="fio", n=64, tol=1e-6, leaf=4, split="polar")),
+    ("fio128polar", dict(kernel="fio", n=128, tol=1e-6, leaf=4, split="polar")),
+    ("fio64ms", dict(kernel="fio", n=64, tol=1e-4, leaf=4, split="multiscale")),
+    ("fio128ms", dict(kernel="fio", n=128, tol=1e-4, leaf=4, split="multiscale")),
+]
+
+
+def serve_multi(main_name, F_main, N_main, dev, nreq=700, seed=1):
+    """Poisson stream over several resident factorizations of uneven N: each
+    request picks a factorization uniformly and has 1..32 RHS; continuous
+    batching per factorization through one mbf_server (4 slots), offered at
+    ~80% of the throughput estimated from solo 32-RHS applies."""
+    import numpy as np
+    import torch
+
+    import mbf_workloads as W
+    import paper_1509_07925_amd as mbf
+
+    t0 = time.time()
+    facs = [(main_name, F_main, N_main)]
+    for name, c in SERVE_EXTRA:
+        if name == main_name:
+            continue
+        n = c["n"]
+        x, xi = (W.grid_x_integer(n), W.grid_omega(n)) if c["kernel"] == "dft" else (W.grid_x_unit(n), W.grid_omega(n))
+        facs.append((name, mbf.Factor.build(x, xi, n, kernel=c["kernel"], tol=c["tol"], leaf_side=c["leaf"],
+                                            split=c["split"], precs=["c64"], max_rank=4096), n * n))
+    log("multi-factor serving: %d factorizations resident (extra builds %.1fs)" % (len(facs), time.time() - t0))
+    rng = np.random.default_rng(seed)
+    which = rng.integers(0, len(facs), size=nreq)
+    sizes = rng.integers(1, 33, size=nreq)
+    pools = [torch.randn((32, N), dtype=torch.complex64, device=dev) for _, _, N in facs]
+    per_rhs = []
+    for (name, F, N), pool in zip(facs, pools):
+        F.apply(pool.t())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3):
+            F.apply(pool.t())
+        torch.cuda.synchronize()
+        per_rhs.append((time.perf_counter() - t1) / (3 * 32))
+    mean_service = float(np.mean([per_rhs[w] * k for w, k in zip(which, sizes)]))
+    rate = 0.8 / mean_service
+    arrivals = W.poisson_arrivals(nreq, rate, seed=seed)
+    ins = [pools[w][: int(k)].t() for w, k in zip(which, sizes)]
+    outs = [torch.empty((int(k), facs[w][2]), dtype=torch.complex64, device=dev).t() for w, k in zip(which, sizes)]
+    srv = mbf.Server(mem_budget=24 << 30, nslots=4, max_batch_rhs=256)
+    ids = []
+    t_start = time.perf_counter()
+    for i in range(nreq):
+        while time.perf_counter() - t_start < arrivals[i]:
+            pass
+        ids.append(srv.submit(facs[which[i]][1], ins[i], outs[i]))
+    srv.drain()
+    lat_ms = np.array([srv.poll(r)[1] / 1e3 for r in ids])
+    st = srv.stats()
+    srv.close()
+    per = {}
+    for j, (name, _, N) in enumerate(facs):
+        sel = lat_ms[which == j]
+        if sel.size:
+            per[name] = {"N": int(N), "requests": int(sel.size), "p50_ms": round(float(np.percentile(sel, 50)), 3),
+                         "p99_ms": round(float(np.percentile(sel, 99)), 3)}
+    return {"factorizations": len(facs), "requests": int(st["requests"]), "rhs": int(st["rhs"]),
+            "batches": int(st["batches"]), "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+            "rhs_per_s": round(st["rhs"] / st["wall_s"], 1) if st["wall_s"] > 0 else None,
+            "offered_rhs_per_s": round(rate * float(np.mean(sizes)), 1),
+            "max_concurrent_batches": int(st["max_concurrent_batches"]), "per_factorization": per}
 
 
 def cpu_baseline(cfg, x, xi, g, u_gpu, out):
