@@ -12,14 +12,17 @@
 // so that D(n, 2m+d) is the real (d=0) / imaginary (d=1) part of out(n, m):
 // output rows are interleaved complex and store coalesced into the state.
 //
-// Tile: 64 or 128 right-hand sides x 64 complex output rows per workgroup
-// (4 waves, each 32 or 64 right-hand sides x 64 real columns), reduction
-// staged through LDS in chunks of 16 or 32 complex entries; the chunk sums
-// are added to the running sums (two-level summation).  Two arithmetic modes:
-//   F32    v_mfma_f32_32x32x2_f32, one complex k per instruction;
-//   BF16X3 v_mfma_f32_32x32x16_bf16, eight complex k per instruction; every
-//          operand is split as hi + lo (both BF16) and the product is
-//          hi*hi + hi*lo + lo*hi with FP32 accumulation.
+// Tiles (variants, chosen per stage shape by the autotuner): 64 to 256
+// right-hand sides x 64 or 128 complex output rows per workgroup of 4 or 8
+// waves; the reduction is staged through LDS in chunks of 16 complex entries,
+// optionally double-buffered.  Arithmetic modes:
+//   F32     v_mfma_f32_32x32x2_f32, one complex k per instruction; the chunk
+//           sums are added to the running sums (two-level summation);
+//   F32 3M  the same instruction on three real products (Gauss), 6 instead
+//           of 8 real flops of matrix-core work per complex multiply-add;
+//   BF16X3  v_mfma_f32_32x32x16_bf16, eight complex k per instruction; every
+//           operand is split as hi + lo (both BF16) and the product is
+//           hi*hi + hi*lo + lo*hi with FP32 accumulation.
 // Workgroup -> tile mapping is XCD-aware: consecutive logical tiles (the
 // right-hand-side tiles of one output tile, then the output tiles of one
 // block) land on the same XCD so that they share its L2.
