@@ -67,30 +67,32 @@ __global__ __launch_bounds__(256) void k_stage_r16(const BlockDesc* __restrict__
   // along the contiguous reduction index)
   const int ak = tid % RK, an = tid / RK;
   const int bm = ADJ ? tid / 4 : tid % RM, bg = ADJ ? tid % 4 : tid / RM;
-  float2 xa;
-  float2 wq[4];
-  auto load = [&](int q0) {
+  struct Regs {
+    float2 x;
+    float2 w[4];
+  };
+  auto load = [&](Regs& g, int q0) {
     const int q = q0 + ak;
-    xa = make_float2(0.f, 0.f);
+    g.x = make_float2(0.f, 0.f);
     if (q < Q && n0 + an < nrhs)
-      xa = in[(int64_t)(n0 + an) * ld_in + (ADJ ? r16_group_row(d, q) : d.in_row + q)];
+      g.x = in[(int64_t)(n0 + an) * ld_in + (ADJ ? r16_group_row(d, q) : d.in_row + q)];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int qq = q0 + 4 * bg + i, m = r0 + bm;
       float2 w = make_float2(0.f, 0.f);
       if (m < R && qq < Q) w = ADJ ? Wb[(int64_t)m * d.M + qq] : Wb[(int64_t)qq * d.M + m];
-      wq[i] = w;
+      g.w[i] = w;
     }
   };
-  auto stash = [&]() {
-    As[0][an * RP + perm(ak)] = xa.x;
-    As[1][an * RP + perm(ak)] = xa.y;
+  auto stash = [&](const Regs& g) {
+    As[0][an * RP + perm(ak)] = g.x.x;
+    As[1][an * RP + perm(ak)] = g.x.y;
     const float s = ADJ ? -1.f : 1.f;
     const int c0 = 2 * bm;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int w = perm(4 * bg + i);
-      const float wr = wq[i].x, wi = s * wq[i].y;
+      const float wr = g.w[i].x, wi = s * g.w[i].y;
       Bs[0][c0 * RP + w] = wr;         // B(2k, 2m)     = Wr
       Bs[0][(c0 + 1) * RP + w] = wi;   // B(2k, 2m+1)   = Wi
       Bs[1][c0 * RP + w] = -wi;        // B(2k+1, 2m)   = -Wi
@@ -101,11 +103,17 @@ __global__ __launch_bounds__(256) void k_stage_r16(const BlockDesc* __restrict__
   const int c = g & 1, half = g >> 1;
   const int wm = wave * 32;  // real columns of this wave
   v4f acc[2] = {v4f{}, v4f{}};
-  load(0);
+  // two chunks ahead in registers: cur (next to stash) and ahead
+  Regs cur, ahead;
+  load(cur, 0);
+  if (RK < Q) load(ahead, RK);
   for (int q0 = 0; q0 < Q; q0 += RK) {
-    stash();
+    stash(cur);
     __syncthreads();
-    if (q0 + RK < Q) load(q0 + RK);
+    if (q0 + RK < Q) {
+      cur = ahead;
+      if (q0 + 2 * RK < Q) load(ahead, q0 + 2 * RK);
+    }
     v4f p[2] = {v4f{}, v4f{}};
 #pragma unroll
     for (int kb = 0; kb < RK; kb += 8) {
