@@ -13,9 +13,9 @@ namespace mbf {
 bool use_mfma(const DevPart& P, int s, int64_t nrhs, int prec);
 
 // Stage kernel variants (tile shape, register prefetch, LDS buffering):
-// 9 for the FP32 kernels (6 on the real embedding, 3 with three real
+// 11 for the FP32 kernels (8 on the real embedding, 3 with three real
 // products), 7 for the split-BF16 kernels.
-inline int num_variants(int prec) { return prec == MBF_C64 ? 9 : 7; }
+inline int num_variants(int prec) { return prec == MBF_C64 ? 11 : 7; }
 
 // force_variant >= 0 bypasses the tuned choice.
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adjoint, const BlockDesc* blk,

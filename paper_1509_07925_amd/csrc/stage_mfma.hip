@@ -107,10 +107,11 @@ __device__ __forceinline__ int bidx_pad(int mrow, int d, int g) { return (2 * mr
 // of 32 right-hand sides x 32 real columns.  PF prefetches the next chunk
 // into registers during the matrix-core work; DB (which implies PF) also
 // double-buffers the LDS so that one barrier per chunk separates the phases.
-template <int TNV_, int TMV_, int NTH_, int RT_, int CT_, bool PF_, bool DB_>
+template <int TNV_, int TMV_, int NTH_, int RT_, int CT_, bool PF_, bool DB_, bool PF2_ = false>
 struct Shape {
   static constexpr int TNV = TNV_, TMV = TMV_, NTH = NTH_, RT = RT_, CT = CT_;
-  static constexpr bool PF = PF_ || DB_, DB = DB_;
+  static constexpr bool PF = PF_ || DB_ || PF2_, DB = DB_;
+  static constexpr bool PF2 = PF2_ && !DB_;  // two chunks of register prefetch (single LDS buffer)
   static constexpr int WR = TNV / (32 * RT);      // waves along right-hand sides
   static constexpr int WC = 2 * TMV / (32 * CT);  // waves along real columns
   static_assert(WR * WC * 64 == NTH, "the waves must cover the tile");
@@ -322,6 +323,20 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
         if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
       }
       compute(cur);
+      __syncthreads();
+    }
+  } else if (S::PF2) {
+    LD ahead;  // chunk q0 + 2 KCH is loading while chunk q0 is summed
+    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+    if (KCH < Q) ahead.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
+    for (int q0 = 0; q0 < Q; q0 += KCH) {
+      stash(0);
+      __syncthreads();
+      if (q0 + KCH < Q) {
+        ld = ahead;
+        if (q0 + 2 * KCH < Q) ahead.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+      }
+      compute(0);
       __syncthreads();
     }
   } else {
@@ -644,6 +659,9 @@ using F5 = Shape<128, 128, 512, 2, 2, true, true>;
 using G6 = Shape3<64, 64, 256, 1, 1, false, false>;
 using G7 = Shape3<64, 64, 256, 1, 1, true, false>;
 using G8 = Shape3<64, 64, 256, 1, 1, true, true>;
+// FP32 with two chunks of register prefetch
+using F9 = Shape<64, 64, 256, 1, 2, true, false, true>;
+using F10 = Shape<128, 64, 256, 2, 2, true, false, true>;
 using B0 = Shape<64, 64, 256, 1, 2, false, false>;
 using B1 = Shape<128, 64, 256, 2, 2, true, false>;
 using B2 = Shape<256, 128, 512, 2, 4, true, false>;
@@ -671,7 +689,9 @@ VariantDims variant_dims(int prec, int v) {
       case 5: return dims_of<F5>();
       case 6: return dims_of<G6>();
       case 7: return dims_of<G7>();
-      default: return dims_of<G8>();
+      case 8: return dims_of<G8>();
+      case 9: return dims_of<F9>();
+      default: return dims_of<F10>();
     }
   }
   switch (v) {
@@ -755,7 +775,9 @@ static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const Blo
       case 5: MBF_LAUNCH(k_stage_f32, float2, F5); break;
       case 6: MBF_LAUNCH(k_stage_f32_3m, float2, G6); break;
       case 7: MBF_LAUNCH(k_stage_f32_3m, float2, G7); break;
-      default: MBF_LAUNCH(k_stage_f32_3m, float2, G8); break;
+      case 8: MBF_LAUNCH(k_stage_f32_3m, float2, G8); break;
+      case 9: MBF_LAUNCH(k_stage_f32, float2, F9); break;
+      default: MBF_LAUNCH(k_stage_f32, float2, F10); break;
     }
   } else {
     switch (v) {

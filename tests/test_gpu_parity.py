@@ -228,7 +228,7 @@ def test_save_load_roundtrip_is_bit_exact(tmp_path):
         _mbf().Factor.load(path)
 
 
-@pytest.mark.parametrize("prec,variant", [("c64", v) for v in range(9)] + [("bf16x3", v) for v in range(7)])
+@pytest.mark.parametrize("prec,variant", [("c64", v) for v in range(11)] + [("bf16x3", v) for v in range(7)])
 def test_every_stage_kernel_variant_is_exact(variant, prec, monkeypatch):
     """The autotuner may pick any variant: all of them must meet the bar.
     300 right-hand sides span several RHS tiles of every width (64, 128, 256)
@@ -283,6 +283,6 @@ def test_autotune_choices_persist_in_tune_file(tmp_path, monkeypatch):
     assert len(lines) == tuned
     for prec_id, adj, rb, qb, nb, v in (tuple(map(int, l)) for l in lines):
         assert prec_id in (1, 2) and adj in (0, 1) and rb >= 1 and qb >= 1 and nb >= 1
-        assert 0 <= v < (9 if prec_id == 1 else 7)
+        assert 0 <= v < (11 if prec_id == 1 else 7)
     _check_both(F, bf, n * n, n * n, 200, "c64", seed=3)
     _check_both(F, bf, n * n, n * n, 200, "bf16x3", seed=4)
