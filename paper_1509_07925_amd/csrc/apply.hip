@@ -15,7 +15,6 @@
 
 #include "device.h"
 #include "stage_mfma.h"
-#include "stage_narrow.h"
 #include "stage_r16.h"
 
 namespace mbf {
@@ -651,10 +650,8 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
                                     P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else if (prec == MBF_C64) {
-        Error e = ni <= 16 ? launch_stage_r16(P, s, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1],
-                                              P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st)
-                           : launch_stage_narrow(P, s, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1],
-                                                 P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
+        Error e = launch_stage_r16(P, s, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni,
+                                   reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
         hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[s & 1],
@@ -683,10 +680,8 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
                                     P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else if (prec == MBF_C64) {
-        Error e = ni <= 16 ? launch_stage_r16(P, s, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
-                                              P.ld[s], ni, reinterpret_cast<const float*>(sc), st)
-                           : launch_stage_narrow(P, s, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
-                                                 P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
+        Error e = launch_stage_r16(P, s, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s], ni,
+                                   reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
         hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[(s + 1) & 1],

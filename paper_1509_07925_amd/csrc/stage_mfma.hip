@@ -15,7 +15,10 @@
 // Tiles (variants, chosen per stage shape by the autotuner): 64 to 256
 // right-hand sides x 64 or 128 complex output rows per workgroup of 4 or 8
 // waves; the reduction is staged through LDS in chunks of 16 complex entries,
-// optionally double-buffered.  Arithmetic modes:
+// optionally with one or two chunks of register prefetch or double-buffered
+// LDS.  Global loads are branch-free (addresses clamped into the block, zero
+// selected outside it), so a chunk's loads are all in flight together.
+// Arithmetic modes:
 //   F32     v_mfma_f32_32x32x2_f32, one complex k per instruction; the chunk
 //           sums are added to the running sums (two-level summation);
 //   F32 3M  the same instruction on three real products (Gauss), 6 instead
@@ -160,22 +163,37 @@ template <class S, bool ADJ, typename WT>
 struct Loader {
   float2 a[S::EA];
   WT b[S::EB][4];
+  // Branch-free: every lane loads from an address clamped into the block
+  // (row, column and right-hand side indices clamped to their last valid
+  // value) and then selects zero where the entry lies outside.  Guarded loads
+  // would each sit in an exec-masked branch, where the compiler waits for
+  // the load to land before the branch closes, serializing the chunk's loads.
+  // Needs R >= 1 (the caller returns earlier otherwise) and Q >= 1, nrhs >= 1
+  // (checked here and by the launcher).
   __device__ __forceinline__ void load(const BlockDesc& d, const float2* __restrict__ in, int64_t ld_in,
                                        const WT* __restrict__ Wb, int R, int Q, int r0, int n0, int q0,
                                        int nrhs) {
     constexpr int NTH = S::NTH, TMV = S::TMV;
     const int tid = threadIdx.x;
+    if (Q <= 0) {  // empty reduction (uniform): nothing to read
+#pragma unroll
+      for (int j = 0; j < S::EA; ++j) a[j] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < S::EB; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[j][i] = WT{};
+      return;
+    }
     {
       const int k = tid % KCH, n = tid / KCH;
       const int q = q0 + k;
-      int32_t row = 0;
-      if (q < Q) row = ADJ ? grp_row(d, q) : d.in_row + q;
+      const int qc = min(q, Q - 1);
+      const int32_t row = ADJ ? grp_row(d, qc) : d.in_row + qc;
 #pragma unroll
       for (int j = 0; j < S::EA; ++j) {
         const int gn = n0 + n + j * (NTH / KCH);
-        float2 v = make_float2(0.f, 0.f);
-        if (gn < nrhs && q < Q) v = in[(int64_t)gn * ld_in + row];
-        a[j] = v;
+        const float2 v = in[(int64_t)min(gn, nrhs - 1) * ld_in + row];
+        a[j] = (gn < nrhs && q < Q) ? v : make_float2(0.f, 0.f);
       }
     }
 #pragma unroll
@@ -183,19 +201,19 @@ struct Loader {
       const int p = tid + j * NTH;
       if (!ADJ) {
         const int m = r0 + p % TMV, q = q0 + 4 * (p / TMV);
+        const int mc = min(m, R - 1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          WT w{};
-          if (m < R && q + i < Q) w = Wb[(int64_t)(q + i) * d.M + m];
-          b[j][i] = w;
+          const WT w = Wb[(int64_t)min(q + i, Q - 1) * d.M + mc];
+          b[j][i] = (m < R && q + i < Q) ? w : WT{};
         }
       } else {
         const int mr = q0 + 4 * (p % 4), kout = r0 + p / 4;
+        const int64_t base = (int64_t)min(kout, R - 1) * d.M;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          WT w{};
-          if (kout < R && mr + i < Q) w = Wb[(int64_t)kout * d.M + mr + i];
-          b[j][i] = w;
+          const WT w = Wb[base + min(mr + i, Q - 1)];
+          b[j][i] = (kout < R && mr + i < Q) ? w : WT{};
         }
       }
     }
@@ -226,7 +244,9 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
                                                       int64_t total) {
   constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
   __shared__ __attribute__((aligned(16))) float As[NB][2][TNV * PA];        // [buf][re|im][n][k]
-  __shared__ __attribute__((aligned(16))) float Bs[NB][2][2 * TMV * PA];  // [buf][plane][bidx_pad]
+  // block operand: [buf][plane][bidx_pad], two planes of 2 TMV x PA words
+  constexpr int BPL = 2 * TMV * PA;
+  __shared__ __attribute__((aligned(16))) float Bs[NB][2 * BPL];
   const Tile tl = map_tile(total, mtiles, ntiles);
   if (tl.b < 0) return;
   const BlockDesc d = blk[tl.b];
@@ -254,12 +274,12 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
       const float2* w = ld.b[j];
       // forward B(2k+c, 2m+d): c=0: (Wr, Wi), c=1: (-Wi, Wr); the adjoint uses conj(W)
       const float s = ADJ ? -1.f : 1.f;
-      *reinterpret_cast<float4*>(&Bs[buf][0][bidx_pad(mrow, 0, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
-      *reinterpret_cast<float4*>(&Bs[buf][0][bidx_pad(mrow, 1, g)]) =
+      *reinterpret_cast<float4*>(&Bs[buf][bidx_pad(mrow, 0, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
+      *reinterpret_cast<float4*>(&Bs[buf][bidx_pad(mrow, 1, g)]) =
           make_float4(s * w[0].y, s * w[1].y, s * w[2].y, s * w[3].y);
-      *reinterpret_cast<float4*>(&Bs[buf][1][bidx_pad(mrow, 0, g)]) =
+      *reinterpret_cast<float4*>(&Bs[buf][BPL + bidx_pad(mrow, 0, g)]) =
           make_float4(-s * w[0].y, -s * w[1].y, -s * w[2].y, -s * w[3].y);
-      *reinterpret_cast<float4*>(&Bs[buf][1][bidx_pad(mrow, 1, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
+      *reinterpret_cast<float4*>(&Bs[buf][BPL + bidx_pad(mrow, 1, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
     }
   };
   // Two-level summation: the matrix cores sum one chunk into p, which is then
@@ -286,7 +306,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         const int col = wm + 32 * c + li;
-        bv[c] = *reinterpret_cast<const float4*>(&Bs[buf][kk][bidx_pad(col >> 1, col & 1, kb >> 2)]);
+        bv[c] = *reinterpret_cast<const float4*>(&Bs[buf][kk * BPL + bidx_pad(col >> 1, col & 1, kb >> 2)]);
       }
       // consecutive instructions go to different accumulator tiles
 #pragma unroll
@@ -709,7 +729,7 @@ VariantDims variant_dims(int prec, int v) {
 
 bool use_mfma(const DevPart&, int, int64_t nrhs, int prec) {
   if (prec == MBF_C64_SPLIT_BF16) return true;
-  if (prec == MBF_C64) return nrhs >= 32;
+  if (prec == MBF_C64) return nrhs > 32;  // up to 32 RHS: the 16 x 16 kernel (stage_r16.hip)
   return false;
 }
 
@@ -799,6 +819,7 @@ Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const Block
   const int Rmax = adj ? P.max_K[s] : P.max_M[s];
   const int Qmax = adj ? P.max_M[s] : P.max_K[s];
   if (prec != MBF_C64 && prec != MBF_C64_SPLIT_BF16) return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel"};
+  if (nrhs < 1) return {MBF_ERR_INVALID_ARG, "MFMA stage: nrhs < 1"};
   const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, adj, Rmax, Qmax, nrhs);
   const VariantDims vd = variant_dims(prec, v);
   const int mtiles = std::max(1, (Rmax + vd.tmv - 1) / vd.tmv);

@@ -93,10 +93,11 @@ def test_dft_n64_correctness_config():
     g = W.rhs(n * n, 1, seed=0)
     assert direct.rel_err(u, direct.dft_fft(n, g)) < 1e-7
     _check_both(F, bf, n * n, n * n, 64, "c64")
-    # few right-hand sides run the streaming FP32 stage kernel (passes of 8,
-    # 16 or 32 columns); the blocks here have up to 4 x 248 rows, i.e. several
-    # 256-row workgroups per block, with a ragged last one
-    for nrhs in (1, 17, 31):
+    # up to 32 right-hand sides run the 16 x 16 matrix-core FP32 stage kernel
+    # (one or two 16-column tiles per workgroup), 33 the 32 x 32 kernels; the
+    # blocks here have up to 4 x 248 rows, i.e. several 64-row workgroups per
+    # block, with a ragged last one
+    for nrhs in (1, 17, 31, 32, 33):
         _check_both(F, bf, n * n, n * n, nrhs, "c64", seed=nrhs)
 
 
