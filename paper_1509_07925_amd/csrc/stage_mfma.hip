@@ -17,7 +17,8 @@
 // waves; the reduction is staged through LDS in chunks of 16 complex entries,
 // optionally with one or two chunks of register prefetch or double-buffered
 // LDS.  Global loads are branch-free (addresses clamped into the block, zero
-// selected outside it), so a chunk's loads are all in flight together.
+// selected when the chunk is moved to LDS), so a chunk's loads are all in
+// flight together and stay in flight during the matrix-core work.
 // Arithmetic modes:
 //   F32     v_mfma_f32_32x32x2_f32, one complex k per instruction; the chunk
 //           sums are added to the running sums (two-level summation);
@@ -163,27 +164,25 @@ template <class S, bool ADJ, typename WT>
 struct Loader {
   float2 a[S::EA];
   WT b[S::EB][4];
+  uint32_t ok;  // bit j: a[j] in range; bit EA + 4 j + i: b[j][i] in range
+  static_assert(S::EA + 4 * S::EB <= 32, "predicate bits");
   // Branch-free: every lane loads from an address clamped into the block
   // (row, column and right-hand side indices clamped to their last valid
-  // value) and then selects zero where the entry lies outside.  Guarded loads
-  // would each sit in an exec-masked branch, where the compiler waits for
-  // the load to land before the branch closes, serializing the chunk's loads.
-  // Needs R >= 1 (the caller returns earlier otherwise) and Q >= 1, nrhs >= 1
-  // (checked here and by the launcher).
+  // value); the entries outside are zeroed by finish(), on a copy made when
+  // the chunk is moved to LDS.  A guarded load would sit in an exec-masked
+  // branch, and a select right after it would consume it: either makes the
+  // compiler wait for the load on the spot, so the prefetch of the next
+  // chunk would not overlap the matrix-core work.  For the same reason the
+  // kernels prefetch unconditionally: a chunk past the end reads clamped
+  // (valid, recently read) addresses and comes out all zero.  Needs R >= 1,
+  // Q >= 1 (the kernels skip the reduction otherwise) and nrhs >= 1 (checked
+  // by the launcher).
   __device__ __forceinline__ void load(const BlockDesc& d, const float2* __restrict__ in, int64_t ld_in,
                                        const WT* __restrict__ Wb, int R, int Q, int r0, int n0, int q0,
                                        int nrhs) {
     constexpr int NTH = S::NTH, TMV = S::TMV;
     const int tid = threadIdx.x;
-    if (Q <= 0) {  // empty reduction (uniform): nothing to read
-#pragma unroll
-      for (int j = 0; j < S::EA; ++j) a[j] = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int j = 0; j < S::EB; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) b[j][i] = WT{};
-      return;
-    }
+    ok = 0;
     {
       const int k = tid % KCH, n = tid / KCH;
       const int q = q0 + k;
@@ -192,8 +191,8 @@ struct Loader {
 #pragma unroll
       for (int j = 0; j < S::EA; ++j) {
         const int gn = n0 + n + j * (NTH / KCH);
-        const float2 v = in[(int64_t)min(gn, nrhs - 1) * ld_in + row];
-        a[j] = (gn < nrhs && q < Q) ? v : make_float2(0.f, 0.f);
+        a[j] = in[(int64_t)min(gn, nrhs - 1) * ld_in + row];
+        ok |= (uint32_t)(gn < nrhs && q < Q) << j;
       }
     }
 #pragma unroll
@@ -204,19 +203,30 @@ struct Loader {
         const int mc = min(m, R - 1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const WT w = Wb[(int64_t)min(q + i, Q - 1) * d.M + mc];
-          b[j][i] = (m < R && q + i < Q) ? w : WT{};
+          b[j][i] = Wb[(int64_t)min(q + i, Q - 1) * d.M + mc];
+          ok |= (uint32_t)(m < R && q + i < Q) << (S::EA + 4 * j + i);
         }
       } else {
         const int mr = q0 + 4 * (p % 4), kout = r0 + p / 4;
         const int64_t base = (int64_t)min(kout, R - 1) * d.M;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const WT w = Wb[base + min(mr + i, Q - 1)];
-          b[j][i] = (kout < R && mr + i < Q) ? w : WT{};
+          b[j][i] = Wb[base + min(mr + i, Q - 1)];
+          ok |= (uint32_t)(kout < R && mr + i < Q) << (S::EA + 4 * j + i);
         }
       }
     }
+  }
+  // Zero the entries outside the block.
+  __device__ __forceinline__ void finish() {
+#pragma unroll
+    for (int j = 0; j < S::EA; ++j)
+      if (!((ok >> j) & 1)) a[j] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < S::EB; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (!((ok >> (S::EA + 4 * j + i)) & 1)) b[j][i] = WT{};
   }
   // LDS row and group of pair j.
   __device__ __forceinline__ static void pair_pos(int j, int& mrow, int& g) {
@@ -261,17 +271,19 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
   using LD = Loader<S, ADJ, float2>;
   LD ld;
   auto stash = [&](int buf) {
+    LD c = ld;
+    c.finish();
     const int k = tid % KCH, n = tid / KCH;
 #pragma unroll
     for (int j = 0; j < S::EA; ++j) {
-      As[buf][0][(n + j * (NTH / KCH)) * PA + k] = ld.a[j].x;
-      As[buf][1][(n + j * (NTH / KCH)) * PA + k] = ld.a[j].y;
+      As[buf][0][(n + j * (NTH / KCH)) * PA + k] = c.a[j].x;
+      As[buf][1][(n + j * (NTH / KCH)) * PA + k] = c.a[j].y;
     }
 #pragma unroll
     for (int j = 0; j < S::EB; ++j) {
       int mrow, g;
       LD::pair_pos(j, mrow, g);
-      const float2* w = ld.b[j];
+      const float2* w = c.b[j];
       // forward B(2k+c, 2m+d): c=0: (Wr, Wi), c=1: (-Wi, Wr); the adjoint uses conj(W)
       const float s = ADJ ? -1.f : 1.f;
       *reinterpret_cast<float4*>(&Bs[buf][bidx_pad(mrow, 0, g)]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
@@ -331,43 +343,42 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[a][c] += p[a][c];
   };
-  if (S::DB) {
-    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    stash(0);
-    if (KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
-    __syncthreads();
-    for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
-      // Buffer cur^1 was last read before the previous barrier: refill it.
-      if (q0 + KCH < Q) {
+  if (Q > 0) {  // (uniform) an empty reduction leaves the sums at zero
+    if (S::DB) {
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+      stash(0);
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
+      __syncthreads();
+      for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
+        // Buffer cur^1 was last read before the previous barrier: refill it
+        // (past the last chunk with zeros that are never read).
         stash(cur ^ 1);
-        if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+        ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+        compute(cur);
+        __syncthreads();
       }
-      compute(cur);
-      __syncthreads();
-    }
-  } else if (S::PF2) {
-    LD ahead;  // chunk q0 + 2 KCH is loading while chunk q0 is summed
-    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    if (KCH < Q) ahead.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
-    for (int q0 = 0; q0 < Q; q0 += KCH) {
-      stash(0);
-      __syncthreads();
-      if (q0 + KCH < Q) {
+    } else if (S::PF2) {
+      LD ahead;  // chunk q0 + 2 KCH is loading while chunk q0 is summed
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+      ahead.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
+      for (int q0 = 0; q0 < Q; q0 += KCH) {
+        stash(0);
+        __syncthreads();
         ld = ahead;
-        if (q0 + 2 * KCH < Q) ahead.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+        ahead.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+        compute(0);
+        __syncthreads();
       }
-      compute(0);
-      __syncthreads();
-    }
-  } else {
-    if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    for (int q0 = 0; q0 < Q; q0 += KCH) {
-      if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
-      stash(0);
-      __syncthreads();
-      if (S::PF && q0 + KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
-      compute(0);
-      __syncthreads();
+    } else {
+      if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+      for (int q0 = 0; q0 < Q; q0 += KCH) {
+        if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+        stash(0);
+        __syncthreads();
+        if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
+        compute(0);
+        __syncthreads();
+      }
     }
   }
   store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
@@ -420,11 +431,13 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32_3m(const BlockDesc* __rest
   using LD = Loader<S, ADJ, float2>;
   LD ld;
   auto stash = [&](int buf) {
+    LD c = ld;
+    c.finish();
     const int k = tid % KCH, n = tid / KCH;
 #pragma unroll
     for (int j = 0; j < S::EA; ++j) {
       const int e = (n + j * (NTH / KCH)) * PA + k;
-      const float2 v = ld.a[j];
+      const float2 v = c.a[j];
       As[buf][0][e] = v.x;
       As[buf][1][e] = v.y;
       As[buf][2][e] = v.x + v.y;
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32_3m(const BlockDesc* __rest
     for (int j = 0; j < S::EB; ++j) {
       int mrow, g;
       LD::pair_pos(j, mrow, g);
-      const float2* w = ld.b[j];
+      const float2* w = c.b[j];
       const float s = ADJ ? -1.f : 1.f;  // B = W (forward) or conj(W) (adjoint)
       const int e = mrow * PA + 4 * g;
       *reinterpret_cast<float4*>(&Bs[buf][0][e]) = make_float4(w[0].x, w[1].x, w[2].x, w[3].x);
@@ -491,28 +504,30 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32_3m(const BlockDesc* __rest
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][a][c] += p[t][a][c];
   };
-  if (S::DB) {
-    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    stash(0);
-    if (KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
-    __syncthreads();
-    for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
-      if (q0 + KCH < Q) {
-        stash(cur ^ 1);
-        if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
-      }
-      compute(cur);
-      __syncthreads();
-    }
-  } else {
-    if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    for (int q0 = 0; q0 < Q; q0 += KCH) {
-      if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+  if (Q > 0) {  // (uniform) an empty reduction leaves the sums at zero
+    if (S::DB) {
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
       stash(0);
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
       __syncthreads();
-      if (S::PF && q0 + KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
-      compute(0);
-      __syncthreads();
+      for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
+        // Buffer cur^1 was last read before the previous barrier: refill it
+        // (past the last chunk with zeros that are never read).
+        stash(cur ^ 1);
+        ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+        compute(cur);
+        __syncthreads();
+      }
+    } else {
+      if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+      for (int q0 = 0; q0 < Q; q0 += KCH) {
+        if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+        stash(0);
+        __syncthreads();
+        if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
+        compute(0);
+        __syncthreads();
+      }
     }
   }
   // Re = T1 - T2, Im = T3 - T1 - T2; lane li holds complex row wm + 32 c + li
@@ -564,12 +579,14 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
   using LD = Loader<S, ADJ, uint2>;
   LD ld;
   auto stash = [&](int buf) {  // registers -> LDS (state split into BF16 hi/lo here)
+    LD c = ld;
+    c.finish();
     const int k = tid % KCH, n = tid / KCH;
 #pragma unroll
     for (int j = 0; j < S::EA; ++j) {
       uint32_t rh, rl, ih, il;
-      split_bf(ld.a[j].x, rh, rl);
-      split_bf(ld.a[j].y, ih, il);
+      split_bf(c.a[j].x, rh, rl);
+      split_bf(c.a[j].y, ih, il);
       Ah[buf][(n + j * (NTH / KCH)) * PA + k] = rh | (ih << 16);
       Al[buf][(n + j * (NTH / KCH)) * PA + k] = rl | (il << 16);
     }
@@ -580,7 +597,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
       uint32_t h0[4], h1[4], l0[4], l1[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint2 w = ld.b[j][i];
+        const uint2 w = c.b[j][i];
         const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
         if (!ADJ) {  // column 2m: (Wr, -Wi);  column 2m+1: (Wi, Wr)
           h0[i] = reh | ((imh ^ 0x8000u) << 16);
@@ -640,29 +657,30 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
         for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
     }
   };
-  if (S::DB) {
-    ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    stash(0);
-    if (KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
-    __syncthreads();
-    for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
-      // Buffer cur^1 was last read before the previous barrier: refill it.
-      if (q0 + KCH < Q) {
-        stash(cur ^ 1);
-        if (q0 + 2 * KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
-      }
-      compute(cur);
-      __syncthreads();
-    }
-  } else {
-    if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
-    for (int q0 = 0; q0 < Q; q0 += KCH) {
-      if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+  if (Q > 0) {  // (uniform) an empty reduction leaves the sums at zero
+    if (S::DB) {
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
       stash(0);
+      ld.load(d, in, ld_in, Wb, R, Q, r0, n0, KCH, nrhs);
       __syncthreads();
-      if (S::PF && q0 + KCH < Q) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
-      compute(0);
-      __syncthreads();
+      for (int q0 = 0, cur = 0; q0 < Q; q0 += KCH, cur ^= 1) {
+        // Buffer cur^1 was last read before the previous barrier: refill it
+        // (past the last chunk with zeros that are never read).
+        stash(cur ^ 1);
+        ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + 2 * KCH, nrhs);
+        compute(cur);
+        __syncthreads();
+      }
+    } else {
+      if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, 0, nrhs);
+      for (int q0 = 0; q0 < Q; q0 += KCH) {
+        if (!S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0, nrhs);
+        stash(0);
+        __syncthreads();
+        if (S::PF) ld.load(d, in, ld_in, Wb, R, Q, r0, n0, q0 + KCH, nrhs);
+        compute(0);
+        __syncthreads();
+      }
     }
   }
   store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);

@@ -81,28 +81,40 @@ __global__ __launch_bounds__(256) void k_stage_r16(const BlockDesc* __restrict__
   struct Regs {
     float2 x[NTN];
     float2 w[4];
+    uint32_t ok;  // bit j: x[j] in range; bit NTN + i: w[i] in range
   };
-  // Branch-free loads: addresses clamped into the block, zero selected
-  // outside it (guarded loads would each wait in their own branch).
+  // Branch-free loads: addresses clamped into the block (a chunk past the
+  // end reads valid, recently read entries); the zeros outside the block are
+  // selected in stash.  A guarded load, or a select right after the load,
+  // would make the compiler wait for it on the spot and the prefetch would
+  // not overlap the matrix-core work.
   auto load = [&](Regs& g, int q0) {
-    const float2 z = make_float2(0.f, 0.f);
     const int q = q0 + ak, qc = min(q, Q - 1);
     const int64_t xr = ADJ ? r16_group_row(d, qc) : d.in_row + qc;
+    g.ok = 0;
 #pragma unroll
     for (int j = 0; j < NTN; ++j) {
       const int n = n0 + an + RT * j;
-      const float2 v = in[(int64_t)min(n, nrhs - 1) * ld_in + xr];
-      g.x[j] = (q < Q && n < nrhs) ? v : z;
+      g.x[j] = in[(int64_t)min(n, nrhs - 1) * ld_in + xr];
+      g.ok |= (uint32_t)(q < Q && n < nrhs) << j;
     }
     const int m = r0 + bm, mc = min(m, R - 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int qq = q0 + 4 * bg + i, qqc = min(qq, Q - 1);
-      const float2 w = ADJ ? Wb[(int64_t)mc * d.M + qqc] : Wb[(int64_t)qqc * d.M + mc];
-      g.w[i] = (m < R && qq < Q) ? w : z;
+      g.w[i] = ADJ ? Wb[(int64_t)mc * d.M + qqc] : Wb[(int64_t)qqc * d.M + mc];
+      g.ok |= (uint32_t)(m < R && qq < Q) << (NTN + i);
     }
   };
-  auto stash = [&](const Regs& g) {
+  auto stash = [&](const Regs& r) {
+    Regs g = r;
+    const float2 z = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < NTN; ++j)
+      if (!((g.ok >> j) & 1)) g.x[j] = z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (!((g.ok >> (NTN + i)) & 1)) g.w[i] = z;
 #pragma unroll
     for (int j = 0; j < NTN; ++j) {
       As[0][(an + RT * j) * RP + perm(ak)] = g.x[j].x;
@@ -129,14 +141,12 @@ __global__ __launch_bounds__(256) void k_stage_r16(const BlockDesc* __restrict__
   // two chunks ahead in registers: cur (next to stash) and ahead
   Regs cur, ahead;
   load(cur, 0);
-  if (RK < Q) load(ahead, RK);
+  load(ahead, RK);
   for (int q0 = 0; q0 < Q; q0 += RK) {
     stash(cur);
     __syncthreads();
-    if (q0 + RK < Q) {
-      cur = ahead;
-      if (q0 + 2 * RK < Q) load(ahead, q0 + 2 * RK);
-    }
+    cur = ahead;
+    load(ahead, q0 + 2 * RK);
     v4f p[NTN][2];
 #pragma unroll
     for (int j = 0; j < NTN; ++j) p[j][0] = p[j][1] = v4f{};
