@@ -174,17 +174,23 @@ __global__ __launch_bounds__(256) void k_leaf_project(const LeafDesc* __restrict
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
     for (int i0 = 0; i0 < d.np; i0 += 64) {
-      for (int e = tid; e < 64 * 32; e += 256) {
-        const int i = e & 63, n = e >> 6;
-        C v = czero<C>();
-        if (i0 + i < d.np && n0 + n < nrhs) v = x[(int64_t)(n0 + n) * ldx + idx[d.p_off + i0 + i]];
-        Xs[i][n] = v;
+      // branch-free: clamped addresses, all loads in flight, zeros selected at the LDS store
+      const int i = tid & 63, ic = min(i0 + i, d.np - 1);
+      const int64_t p = idx[d.p_off + ic];
+      C xv[8], fv[16];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) xv[r] = x[(int64_t)min(n0 + (tid >> 6) + 4 * r, nrhs - 1) * ldx + p];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) fv[r] = Fb[(int64_t)min(k0 + (tid >> 6) + 4 * r, d.r - 1) * d.np + ic];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int n = (tid >> 6) + 4 * r;
+        Xs[i][n] = (i0 + i < d.np && n0 + n < nrhs) ? xv[r] : czero<C>();
       }
-      for (int e = tid; e < 64 * 64; e += 256) {
-        const int i = e & 63, k = e >> 6;
-        C v = czero<C>();
-        if (i0 + i < d.np && k0 + k < d.r) v = cconj(Fb[(int64_t)(k0 + k) * d.np + i0 + i]);
-        Fs[i][k] = v;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k = (tid >> 6) + 4 * r;
+        Fs[i][k] = (i0 + i < d.np && k0 + k < d.r) ? cconj(fv[r]) : czero<C>();
       }
       __syncthreads();
       const int ilim = min(64, d.np - i0);
@@ -298,12 +304,18 @@ __global__ __launch_bounds__(256) void k_leaf_project_wide(const LeafDesc* __res
   C acc[NRW];
 #pragma unroll
   for (int n = 0; n < NRW; ++n) acc[n] = czero<C>();
+  // The NRW loads of a point are issued together (right-hand sides past nrhs
+  // read the last one again; their sums are not stored): a guarded load
+  // would wait for its data before the next one is issued.
+#pragma unroll 2
   for (int i = lane; i < d.np; i += 64) {
     const C f = cconj(Fk[i]);
     const int64_t p = idx[d.p_off + i];
+    C xv[NRW];
 #pragma unroll
-    for (int n = 0; n < NRW; ++n)
-      if (n < nn) cfma(acc[n], f, x[(int64_t)(n0 + n) * ldx + p]);
+    for (int n = 0; n < NRW; ++n) xv[n] = x[(int64_t)min(n0 + n, nrhs - 1) * ldx + p];
+#pragma unroll
+    for (int n = 0; n < NRW; ++n) cfma(acc[n], f, xv[n]);
   }
 #pragma unroll
   for (int n = 0; n < NRW; ++n)
@@ -491,45 +503,64 @@ __global__ __launch_bounds__(256) void k_center_fwd(const typename cx<T>::t* __r
   }
 }
 
-// Adjoint of the dense center, pass 1: partial[chunk, k, n] = sum over the
-// chunk's rows i of conj(KC[i + k nx]) h[i, n].  One workgroup per
-// (chunk of 4096 rows, k tile of 64, n tile of 4).
+// Adjoint of the dense center, pass 1: partial[chunk, n, k] = sum over the
+// chunk's rows i of conj(KC[i + k nx]) h[i, n].  One workgroup per (chunk of
+// rows, 64 center columns k, 16 right-hand sides).  The chunk is walked in
+// slabs of 64 rows staged in LDS, loaded along the rows (the contiguous index
+// of both KC and h; addresses clamped into range, zeros selected at the
+// LDS store); thread (k = tid % 64, group g = tid / 64) sums right-hand sides
+// 4 g .. 4 g + 3, reading KC from its LDS row and h as a broadcast.
 template <typename T>
 __global__ __launch_bounds__(256) void k_center_adj_partial(const typename cx<T>::t* __restrict__ KC,
                                                             int64_t nx, int32_t nc,
                                                             const typename cx<T>::t* __restrict__ h,
-                                                            int64_t ldh, int nrhs,
+                                                            int64_t ldh, int nrhs, int64_t chunk_rows,
                                                             typename cx<T>::t* __restrict__ part) {
   using C = typename cx<T>::t;
-  constexpr int CH = 4096;
-  __shared__ C red[4][64][5];
-  const int k = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int w = threadIdx.x >> 6;  // 4 row slices
-  const int64_t i0 = (int64_t)blockIdx.x * CH;
-  const int n0 = blockIdx.z * 4;
+  __shared__ C Ks[64][65];  // [k][i], conj(KC)
+  __shared__ C Hs[64][17];  // [i][n]
+  const int tid = threadIdx.x, kk = tid & 63, g = tid >> 6;
+  const int k0 = blockIdx.y * 64, n0 = blockIdx.z * 16;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk_rows, i1 = min(i0 + chunk_rows, nx);
   C acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = czero<C>();
-  if (k < nc) {
-    for (int64_t i = i0 + w; i < min(i0 + CH, nx); i += 4) {
-      const C f = cconj(KC[(int64_t)k * nx + i]);
+  for (int64_t sl = i0; sl < i1; sl += 64) {
+    C kv[16], hv[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (n0 + j < nrhs) cfma(acc[j], f, h[(int64_t)(n0 + j) * ldh + i]);
+    for (int r = 0; r < 16; ++r) {  // KC slab: 64 k x 64 rows, lanes along the rows
+      const int e = tid + 256 * r, k = e >> 6, i = e & 63;
+      kv[r] = KC[(int64_t)min(k0 + k, nc - 1) * nx + min(sl + i, i1 - 1)];
     }
-  }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) red[w][threadIdx.x & 63][j] = acc[j];
-  __syncthreads();
-  if (w == 0 && k < nc) {
+    for (int r = 0; r < 4; ++r) {  // h slab: 64 rows x 16 RHS
+      const int e = tid + 256 * r, n = e >> 6, i = e & 63;
+      hv[r] = h[(int64_t)min(n0 + n, nrhs - 1) * ldh + min(sl + i, i1 - 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = tid + 256 * r, k = e >> 6, i = e & 63;
+      Ks[k][i] = (k0 + k < nc && sl + i < i1) ? cconj(kv[r]) : czero<C>();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r, n = e >> 6, i = e & 63;
+      Hs[i][n] = (n0 + n < nrhs && sl + i < i1) ? hv[r] : czero<C>();
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int i = 0; i < 64; ++i) {
+      const C f = Ks[kk][i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cfma(acc[j], f, Hs[i][4 * g + j]);
+    }
+    __syncthreads();
+  }
+  if (k0 + kk < nc) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      C s = red[0][threadIdx.x & 63][j];
-      for (int q = 1; q < 4; ++q) {
-        s.x += red[q][threadIdx.x & 63][j].x;
-        s.y += red[q][threadIdx.x & 63][j].y;
-      }
-      if (n0 + j < nrhs) part[((int64_t)blockIdx.x * nrhs + n0 + j) * nc + k] = s;
+      const int n = n0 + 4 * g + j;
+      if (n < nrhs) part[((int64_t)blockIdx.x * nrhs + n) * nc + k0 + kk] = acc[j];
     }
   }
 }
@@ -696,6 +727,13 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   return hip_check("apply launch");
 }
 
+// Rows per chunk of the center adjoint's first pass: at least 512, and at most
+// 128 chunks (the partial sums take chunks x n_center x nrhs entries).
+inline int64_t center_chunk_rows(int64_t nx) {
+  const int64_t per = (nx + 127) / 128;
+  return std::max<int64_t>(512, (per + 63) / 64 * 64);
+}
+
 template <typename T>
 Error run_center(const DevFactor& F, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
                  void* out, int64_t ldout, void* ws, bool accumulate, hipStream_t st) {
@@ -710,10 +748,11 @@ Error run_center(const DevFactor& F, int prec, bool adj, int64_t nrhs, const voi
                        st, KC, F.d_center_idx, F.nx, nc, reinterpret_cast<const C*>(in), ldin,
                        reinterpret_cast<C*>(out), ldout, ni, accumulate ? 1 : 0);
   } else {
-    const int nchunk = (int)((F.nx + 4095) / 4096);
+    const int64_t ch = center_chunk_rows(F.nx);
+    const int nchunk = (int)((F.nx + ch - 1) / ch);
     C* part = reinterpret_cast<C*>(ws);
-    hipLaunchKernelGGL(k_center_adj_partial<T>, dim3(nchunk, (nc + 63) / 64, (unsigned)((nrhs + 3) / 4)),
-                       dim3(256), 0, st, KC, F.nx, nc, reinterpret_cast<const C*>(in), ldin, ni, part);
+    hipLaunchKernelGGL(k_center_adj_partial<T>, dim3(nchunk, (nc + 63) / 64, (unsigned)((nrhs + 15) / 16)),
+                       dim3(256), 0, st, KC, F.nx, nc, reinterpret_cast<const C*>(in), ldin, ni, ch, part);
     hipLaunchKernelGGL(k_center_adj_reduce<T>, dim3((unsigned)(((int64_t)nc * nrhs + 255) / 256)),
                        dim3(256), 0, st, part, nchunk, nc, F.d_center_idx, reinterpret_cast<C*>(out),
                        ldout, ni);
@@ -761,7 +800,8 @@ size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs) {
   const size_t es = prec == MBF_C128 ? 16 : 8;
   size_t b = 2 * (size_t)state_ld_max(F) * (size_t)nrhs * es;
   if (F.n_center > 0) {
-    const size_t nchunk = (size_t)((F.nx + 4095) / 4096);
+    const int64_t ch = center_chunk_rows(F.nx);
+    const size_t nchunk = (size_t)((F.nx + ch - 1) / ch);
     b = std::max(b, nchunk * (size_t)F.n_center * (size_t)nrhs * es);
   }
   return (b + 255) / 256 * 256;
