@@ -242,21 +242,31 @@ __global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __rest
   C acc[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) acc[j] = czero<C>();
+  // Branch-free loads (clamped addresses): the Z slab's loads are issued
+  // together, and F is read 8 reduction entries at a time; rows of Zs past
+  // the rank are zero, so the last group of 8 needs no guard.  Lanes past the
+  // leaf's last point compute on a clamped point and are not stored.
+  const int ic = min(i0 + ti, d.np - 1);
   for (int k0 = 0; k0 < d.r; k0 += 64) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int k = e & 63, n = e >> 6;
-      C v = czero<C>();
-      if (k0 + k < d.r && n0 + n < nrhs) v = z[(int64_t)(n0 + n) * ldz + d.row + k0 + k];
-      Zs[k][n] = v;
+    C zv[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      zv[r] = z[(int64_t)min(n0 + tn + 4 * r, nrhs - 1) * ldz + d.row + min(k0 + ti, d.r - 1)];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int n = tn + 4 * r;
+      Zs[ti][n] = (k0 + ti < d.r && n0 + n < nrhs) ? zv[r] : czero<C>();
     }
     __syncthreads();
-    if (i0 + ti < d.np) {
-      const int klim = min(64, d.r - k0);
-      for (int k = 0; k < klim; ++k) {
-        const C f = Fb[(int64_t)(k0 + k) * d.np + i0 + ti];
+    const int klim = min(64, d.r - k0);
+    for (int k = 0; k < klim; k += 8) {
+      C f[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) cfma(acc[j], f, Zs[k][tn + 4 * j]);
-      }
+      for (int u = 0; u < 8; ++u) f[u] = Fb[(int64_t)min(k0 + k + u, d.r - 1) * d.np + ic];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cfma(acc[j], f[u], Zs[k + u][tn + 4 * j]);
     }
     __syncthreads();
   }
