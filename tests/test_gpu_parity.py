@@ -116,10 +116,13 @@ def test_multiscale_fio_parity():
     n = 64
     x, xi = W.grid_x_unit(n), W.grid_omega(n)
     ms = butterfly.build_multiscale(kernels.fio_radon(n), x, xi, n, ((0, 0), 1.0), 1e-6, 10 ** 6, leaf_side=4)
-    parts = [_import(bf, ["c64"]) for _, _, bf in ms.parts]
+    parts = [_import(bf, ["c64", "c128"]) for _, _, bf in ms.parts]
     F = mbf.multiscale_assemble(parts, [idx for _, idx, _ in ms.parts], n * n, ms.center_idx, ms.KC,
-                                precs=["c64"])
+                                precs=["c64", "c128"])
     _check_both(F, ms, n * n, n * n, 16, "c64")
+    # 20 RHS: the center adjoint's second 16-RHS tile is ragged (FP32 and FP64 kernels)
+    _check_both(F, ms, n * n, n * n, 20, "c64", seed=20)
+    _check_both(F, ms, n * n, n * n, 20, "c128", seed=22)
 
 
 @pytest.mark.parametrize("prec,nrhs", [("c64", 40), ("c64", 7), ("bf16x3", 40), ("c128", 9)])
