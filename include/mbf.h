@@ -111,8 +111,18 @@ int mbf_kernel_fio(void* user, int64_t m, const int64_t* rows, int64_t k, const 
  *   oversample random-sampling oversampling (extra rows / columns).
  *   seed       seed of the random sampling.
  *   prec_mask  bit (1 << mbf_prec) for every precision to keep on device.
- *   threads    host threads for the build (0 = OMP_NUM_THREADS when set,
- *              else the CPUs in the process's affinity mask).             */
+ *   threads    host threads of the host builder (0 = OMP_NUM_THREADS when
+ *              set, else the CPUs in the process's affinity mask).
+ *   builder    MBF_BUILD_HOST: FP64 on the host, any entry callback.
+ *              MBF_BUILD_DEVICE: FP64 on the current HIP device; the entries
+ *              are evaluated on the device, so the callback must be one of
+ *              the ready-made kernels (mbf_kernel_dft / mbf_kernel_fio) and
+ *              tol >= 1e-7 (its orthonormal bases come from Gram matrices,
+ *              which resolve singular values down to about 1e-8 of the
+ *              largest).  Otherwise MBF_ERR_UNSUPPORTED.
+ *   device_mem_gb  MBF_BUILD_DEVICE: bound on the builder's scratch memory
+ *              (GB; 0 = 48).  The finished factors are not counted.       */
+typedef enum { MBF_BUILD_HOST = 0, MBF_BUILD_DEVICE = 1 } mbf_builder;
 typedef struct {
   double tol;
   int32_t max_rank;
@@ -125,6 +135,8 @@ typedef struct {
   uint64_t seed;
   uint32_t prec_mask;
   int32_t threads;
+  int32_t builder;
+  int32_t device_mem_gb;
 } mbf_opts;
 
 /* Build a factorization from point sets and an entry callback (Section 2,
@@ -134,10 +146,17 @@ typedef struct {
  * form eq. (lowrank2)); polar (Section 3.2) or multiscale (Section 4.2)
  * splits per opts->split.  x: nx points, xi: nxi points, 2 doubles each
  * (host memory, read during the call only).  The build runs in FP64 on the
- * host; the packed factors are copied to the current HIP device on `stream`
- * before the call returns.  Errors: MBF_ERR_INVALID_ARG (bad sizes or
- * options), MBF_ERR_CALLBACK (callback returned nonzero; nothing leaks),
- * MBF_ERR_OOM, MBF_ERR_HIP. */
+ * host or on the current HIP device (opts->builder); the factors are left
+ * on the device in every precision of opts->prec_mask before the call
+ * returns (the call synchronizes the device).  The device builder follows
+ * the same steps: the random-sampling SVD of every middle-level block
+ * (representative columns and rows by pivoted QR of sampled blocks,
+ * orthonormal bases of the representative columns and rows, the middle
+ * matrix from a sampled sub-block, its SVD), then the recursive truncated
+ * SVDs of the merged blocks, level by level.  Errors: MBF_ERR_INVALID_ARG
+ * (bad sizes or options), MBF_ERR_CALLBACK (callback returned nonzero;
+ * nothing leaks), MBF_ERR_UNSUPPORTED (device builder with another
+ * callback or tol < 1e-7), MBF_ERR_OOM, MBF_ERR_HIP. */
 mbf_status mbf_build(int32_t dim, int64_t nx, const double* x, int64_t nxi, const double* xi,
                      mbf_entry_cb cb, void* user, const mbf_opts* opts, void* stream,
                      mbf_factor* out);
@@ -274,23 +293,39 @@ mbf_status mbf_profile_begin(mbf_factor f, int32_t max_launches);
 mbf_status mbf_profile_end(mbf_factor f, mbf_launch_record* out, int32_t cap, int32_t* count);
 
 /* Serving: a request loop over resident factorizations with continuous
- * batching and memory admission.  mbf_server_create reserves mem_budget
- * bytes of device memory (the only allocation of the server) and nslots
- * HIP streams (default priority).  A dispatcher thread forms batches from
- * queued requests on the same (factor, precision), up to max_batch_rhs
- * columns; a batch is admitted when a slot is free and the pool can hold
- * its staging (g and u blocks) and workspace; batches on different slots
- * run concurrently.  Requests that arrive while others are on the GPU join
- * the next batches as slots and memory free up.
+ * batching and memory admission (no passage of the paper: the batched,
+ * served form of eq. (gbf)'s apply).  mbf_server_create reserves
+ * mem_budget bytes of device memory (the only allocation of the server) and
+ * nslots HIP streams (default priority).  A dispatcher thread forms batches
+ * from queued requests on the same (factor, precision), up to max_batch_rhs
+ * columns; a batch is admitted when a slot is free and the pool can hold its
+ * staging (g and u blocks) and workspace; batches on different slots run
+ * concurrently.  Requests that arrive while others are on the GPU join the
+ * next batches as slots and memory free up.  When several queued requests
+ * together exceed the pool, the later ones wait for a following batch; only
+ * a request that cannot fit the whole budget on its own fails.
  *   submit: u = K g for one request (device pointers owned by the caller,
  *           unchanged until the request completes); returns its id.
- *   poll:   *done = 1 once u holds the result; latency = completion -
- *           submission on the host clock (microseconds).  A request that
- *           can never fit the budget completes with MBF_ERR_OOM.
- *   drain:  waits until every submitted request has completed.
- *   stats:  p50 / p99 / mean latency, requests, RHS, batches, the largest
- *           number of batches in flight at once, wall time first submit ->
- *           last completion.
+ *           Readiness: the server's streams do not follow the caller's
+ *           streams.  If g is produced by device work that may still be
+ *           running, pass an event recorded after that work as ready_event
+ *           (hipEvent_t as void*; it must stay valid until the request
+ *           completes): the batch waits for it before reading g.  With
+ *           ready_event = NULL, g must already be complete on the device.
+ *   poll:   *done = 1 once u holds the result, and the request's record is
+ *           then released; latency = completion - submission on the host
+ *           clock (microseconds).  A request that failed reports *done = 1
+ *           and returns its error: MBF_ERR_OOM when it can never fit the
+ *           budget, MBF_ERR_HIP when its batch could not be enqueued or
+ *           failed on the device (u is then undefined).  An id that was never
+ *           issued or whose completion was already reported returns
+ *           MBF_ERR_INVALID_ARG.  At most 2^20 unpolled records are kept (the
+ *           oldest are dropped beyond that).
+ *   drain:  waits until every submitted request has completed; returns
+ *           MBF_ERR_HIP if any batch failed since the server was created.
+ *   stats:  p50 / p99 / mean latency over the last 2^20 successful requests,
+ *           requests, RHS, batches, the largest number of batches in flight
+ *           at once, wall time first submit -> last completion.
  * A factor must outlive every request that names it.  Submit, poll, drain
  * and stats may be called from any host thread. */
 typedef struct mbf_server_s* mbf_server;
@@ -300,7 +335,7 @@ typedef struct {
 } mbf_server_stats_t;
 mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, mbf_server* out);
 mbf_status mbf_server_submit(mbf_server s, mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg,
-                             void* u, int64_t ldu, uint64_t* id);
+                             void* u, int64_t ldu, void* ready_event, uint64_t* id);
 mbf_status mbf_server_poll(mbf_server s, uint64_t id, int32_t* done, double* latency_us);
 mbf_status mbf_server_drain(mbf_server s);
 mbf_status mbf_server_stats(mbf_server s, mbf_server_stats_t* out);

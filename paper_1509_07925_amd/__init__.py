@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmbf.so")
 
 PREC = {"c128": 0, "c64": 1, "bf16x3": 2}
 SPLIT = {"none": 0, "polar": 1, "multiscale": 2}
+BUILDER = {"host": 0, "device": 1}
 
 _lib = None
 
@@ -33,7 +34,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_rank", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("leaf_side", ctypes.c_int32), ("grid_n", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("center_side", ctypes.c_int32), ("oversample", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("prec_mask", ctypes.c_uint32), ("threads", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("prec_mask", ctypes.c_uint32), ("threads", ctypes.c_int32),
+                ("builder", ctypes.c_int32), ("device_mem_gb", ctypes.c_int32)]
 
 
 class _KParams(ctypes.Structure):
@@ -99,7 +101,7 @@ def lib():
     L.mbf_profile_begin.argtypes = [vp, i32]
     L.mbf_profile_end.argtypes = [vp, ctypes.POINTER(LaunchRecord), i32, ctypes.POINTER(i32)]
     L.mbf_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.POINTER(vp)]
-    L.mbf_server_submit.argtypes = [vp, vp, i32, i64, vp, i64, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
+    L.mbf_server_submit.argtypes = [vp, vp, i32, i64, vp, i64, vp, i64, vp, ctypes.POINTER(ctypes.c_uint64)]
     L.mbf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     L.mbf_server_drain.argtypes = [vp]
     L.mbf_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -168,13 +170,18 @@ class Factor:
 
     @classmethod
     def build(cls, x, xi, n, kernel="dft", c_scale=1.0, tol=1e-6, max_rank=1024, leaf_side=4, depth=0,
-              split="none", center_side=16, oversample=10, seed=0, precs=("c64",), threads=0):
+              split="none", center_side=16, oversample=10, seed=0, precs=("c64",), threads=0, builder=None,
+              device_mem_gb=0):
         """mbf_build from point sets and a kernel-entry callback.
 
         ``kernel`` is "dft", "fio" (built-in C callbacks) or a Python
         callable f(rows, cols) -> complex128 array (rows x cols) taking
-        index arrays into x / xi.
+        index arrays into x / xi.  ``builder`` is "device" (FP64 on the GPU;
+        built-in kernels only, tol >= 1e-7) or "host"; by default built-in
+        kernels build on the device and Python callables on the host.
         """
+        if builder is None:
+            builder = "device" if kernel in ("dft", "fio") else "host"
         x = np.ascontiguousarray(x, np.float64)
         xi = np.ascontiguousarray(xi, np.float64)
         L = lib()
@@ -205,7 +212,7 @@ class Factor:
             threads = 1  # Python callbacks hold the GIL
         keep.append(cb)
         o = _Opts(tol, max_rank, depth, leaf_side, n, SPLIT[split], center_side, oversample, seed,
-                  _mask(precs), threads)
+                  _mask(precs), threads, BUILDER[builder], device_mem_gb)
         h = ctypes.c_void_p()
         _check(L.mbf_build(2, x.shape[0], x.ctypes.data, xi.shape[0], xi.ctypes.data, cb, user,
                            ctypes.byref(o), None, ctypes.byref(h)))
@@ -330,8 +337,14 @@ class Server:
         _check(lib().mbf_server_create(int(mem_budget), nslots, max_batch_rhs, ctypes.byref(self._h)))
         self._live = {}
 
-    def submit(self, factor, g, out, prec="c64"):
-        """Queue u = K g (g, out: column-major CUDA tensors); returns the request id."""
+    def submit(self, factor, g, out, prec="c64", ready=True):
+        """Queue u = K g (g, out: column-major CUDA tensors); returns the request id.
+
+        With ``ready=True`` an event is recorded on the current stream and
+        the request's batch waits for it before reading g (work that
+        produced g on that stream is ordered before the request).
+        """
+        import torch
         G = g.reshape(-1, 1) if g.dim() == 1 else g
         O = out.reshape(-1, 1) if out.dim() == 1 else out
         nrhs = G.shape[1]
@@ -339,18 +352,26 @@ class Server:
             raise ValueError("column-major tensors with matching columns required")
         ldg = G.stride(1) if nrhs > 1 else G.shape[0]
         ldo = O.stride(1) if nrhs > 1 else O.shape[0]
+        ev = None
+        if ready:
+            ev = torch.cuda.Event()
+            ev.record()
         rid = ctypes.c_uint64()
         _check(lib().mbf_server_submit(self._h, factor._h, PREC[prec], nrhs, ctypes.c_void_p(G.data_ptr()), ldg,
-                                       ctypes.c_void_p(O.data_ptr()), ldo, ctypes.byref(rid)))
-        self._live[rid.value] = (factor, g, out)
+                                       ctypes.c_void_p(O.data_ptr()), ldo,
+                                       ctypes.c_void_p(ev.cuda_event) if ev is not None else None,
+                                       ctypes.byref(rid)))
+        self._live[rid.value] = (factor, g, out, ev)
         return rid.value
 
     def poll(self, rid):
+        """(done, latency_us); raises MBFError when the request failed."""
         done = ctypes.c_int32()
         lat = ctypes.c_double()
-        _check(lib().mbf_server_poll(self._h, rid, ctypes.byref(done), ctypes.byref(lat)))
+        st = lib().mbf_server_poll(self._h, rid, ctypes.byref(done), ctypes.byref(lat))
         if done.value:
             self._live.pop(rid, None)
+        _check(st)
         return bool(done.value), lat.value
 
     def drain(self):

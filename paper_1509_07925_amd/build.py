@@ -31,6 +31,10 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
+def _rocm():
+    return os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
 def _compile(src):
     obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
     if src.endswith(".hip"):
@@ -49,7 +53,9 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
+    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
+        "-L" + os.path.join(_rocm(), "lib"), "-Wl,-rpath," + os.path.join(_rocm(), "lib"), "-lrocsolver", "-lrocblas",
+        "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

@@ -637,7 +637,6 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   using C = typename cx<T>::t;
   const PrecData& pd = P.prec[prec];
   C* buf[2] = {reinterpret_cast<C*>(ws), reinterpret_cast<C*>(ws) + ws_ld * nrhs};
-  const C* W = reinterpret_cast<const C*>(pd.W);
   const T* S = reinterpret_cast<const T*>(pd.S);
   const int L = P.L, m = P.m;
   const unsigned nt = ntiles(nrhs);
@@ -687,15 +686,16 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       stage_cost(s, fl, by);
       Timed t(pr, st, 1, pidx, s, prec, fl, by);
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
-        Error e = launch_stage_mfma(P, s, prec, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1],
+        Error e = launch_stage_mfma(P, s, prec, false, bd, pd.Wst[s], buf[s & 1], P.ld[s], buf[(s + 1) & 1],
                                     P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else if (prec == MBF_C64) {
-        Error e = launch_stage_r16(P, s, false, bd, pd.W, buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni,
+        Error e = launch_stage_r16(P, s, false, bd, pd.Wst[s], buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni,
                                    reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
-        hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[s & 1],
+        hipLaunchKernelGGL((k_stage<T, false>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd,
+                           reinterpret_cast<const C*>(pd.Wst[s]), buf[s & 1],
                            P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni, sc);
       }
     }
@@ -717,15 +717,16 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       stage_cost(s, fl, by);
       Timed t(pr, st, 1, pidx, s, prec, fl, by);
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
-        Error e = launch_stage_mfma(P, s, prec, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
+        Error e = launch_stage_mfma(P, s, prec, true, bd, pd.Wst[s], buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
                                     P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else if (prec == MBF_C64) {
-        Error e = launch_stage_r16(P, s, true, bd, pd.W, buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s], ni,
+        Error e = launch_stage_r16(P, s, true, bd, pd.Wst[s], buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s], ni,
                                    reinterpret_cast<const float*>(sc), st);
         if (e.st != MBF_OK) return e;
       } else {
-        hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd, W, buf[(s + 1) & 1],
+        hipLaunchKernelGGL((k_stage<T, true>), dim3(P.nblk[s], nt), dim3(256), 0, st, bd,
+                           reinterpret_cast<const C*>(pd.Wst[s]), buf[(s + 1) & 1],
                            P.ld[s + 1], buf[s & 1], P.ld[s], ni, sc);
       }
     }
@@ -794,9 +795,9 @@ Error autotune_factor(const DevFactor& F, int prec, int64_t nrhs, void* ws, size
       if (P.nblk[s] == 0 || !use_mfma(P, s, nrhs, prec)) continue;
       const BlockDesc* bd = P.d_blk + P.blk_first[s];
       for (int adj = 0; adj < 2; ++adj) {
-        Error e = adj ? autotune_stage(P, s, prec, true, bd, P.prec[prec].W, buf[(s + 1) & 1], P.ld[s + 1],
+        Error e = adj ? autotune_stage(P, s, prec, true, bd, P.prec[prec].Wst[s], buf[(s + 1) & 1], P.ld[s + 1],
                                        buf[s & 1], P.ld[s], (int)nrhs, st, nullptr, nullptr)
-                      : autotune_stage(P, s, prec, false, bd, P.prec[prec].W, buf[s & 1], P.ld[s],
+                      : autotune_stage(P, s, prec, false, bd, P.prec[prec].Wst[s], buf[s & 1], P.ld[s],
                                        buf[(s + 1) & 1], P.ld[s + 1], (int)nrhs, st, nullptr, nullptr);
         if (e.st != MBF_OK) return e;
         if (ntuned) ++*ntuned;

@@ -25,6 +25,7 @@
 #include <sched.h>
 #include <cstdlib>
 
+#include "gpu_build.h"
 #include "linalg.h"
 
 namespace mbf {
@@ -267,6 +268,8 @@ bool validate_opts(const mbf_opts& o, std::string& why) {
     return why = "center_side must be a power of two >= 2", false;
   if (o.oversample < 0) return why = "oversample must be >= 0", false;
   if ((o.prec_mask & 7u) == 0) return why = "empty precision mask", false;
+  if (o.builder != MBF_BUILD_HOST && o.builder != MBF_BUILD_DEVICE) return why = "unknown builder", false;
+  if (o.device_mem_gb < 0) return why = "device_mem_gb must be >= 0", false;
   return true;
 }
 
@@ -524,12 +527,43 @@ Error finish_part(const HostFactor& f, const int64_t* idx_map, uint32_t mask, De
   return {MBF_OK, ""};
 }
 
+Error finish_device_part(const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
+                         const std::vector<int64_t>& os, const DeviceKernel& K, const mbf_opts& o, DevFactor& F) {
+  F.parts.emplace_back();
+  Error e = build_part_device(xt, ot, xs, os, K, o, F.prec_mask, F.parts.back());
+  if (e.st != MBF_OK) return e;
+  F.nnz += F.parts.back().nnz;
+  for (auto& p : F.parts.back().prec) F.device_bytes += p.bytes;
+  return {MBF_OK, ""};
+}
+
 }  // namespace
 
 Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, mbf_entry_cb cb, void* user,
                    const mbf_opts& o, DevFactor& F) {
   const int64_t n = o.grid_n;
   if (nx != n * n || nxi != n * n) return {MBF_ERR_INVALID_ARG, "points must form n x n grids (grid_n)"};
+  // Device builder: the entries are evaluated on the GPU, so the kernel must
+  // be one the device knows (the ready-made callbacks).
+  const bool dev = o.builder == MBF_BUILD_DEVICE;
+  DeviceKernel DK;
+  if (dev) {
+    const auto* kp = static_cast<const mbf_kernel_params*>(user);
+    if (cb == mbf_kernel_dft)
+      DK.kind = 0;
+    else if (cb == mbf_kernel_fio)
+      DK.kind = 1;
+    else
+      return {MBF_ERR_UNSUPPORTED, "the device builder evaluates only mbf_kernel_dft / mbf_kernel_fio"};
+    if (!kp || !kp->x || !kp->xi || kp->n <= 0) return {MBF_ERR_INVALID_ARG, "missing kernel parameters"};
+    if (!(o.tol >= 1e-7)) return {MBF_ERR_UNSUPPORTED, "the device builder needs tol >= 1e-7"};
+    DK.n = kp->n;
+    DK.c_scale = kp->c_scale;
+    DK.x = kp->x;
+    DK.xi = kp->xi;
+    DK.nx = nx;
+    DK.nxi = nxi;
+  }
   F.nx = nx;
   F.nxi = nxi;
   F.prec_mask = o.prec_mask & 7u;
@@ -564,6 +598,7 @@ Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, m
     }
     Tree xt = tree_from_leaf_codes(L, nx, xc.data());
     Tree ot = tree_from_leaf_codes(L, nxi, oc.data());
+    if (dev) return finish_device_part(xt, ot, xs, os, DK, o, F);
     HostFactor f = build_host(xt, ot, xs, os, cb, user, o);
     return finish_part(f, nullptr, F.prec_mask, F);
   }
@@ -592,6 +627,11 @@ Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, m
     std::vector<int64_t> oc = grid_leaf_codes(b1, b2, 2 * a, Lt);
     Tree xt = tree_from_leaf_codes(Lt, nx, xc.data());
     Tree ot = tree_from_leaf_codes(Lt, (int64_t)idx.size(), oc.data());
+    if (dev) {
+      Error e = finish_device_part(xt, ot, xs, idx, DK, o, F);
+      if (e.st != MBF_OK) return e;
+      continue;
+    }
     HostFactor f = build_host(xt, ot, xs, idx, cb, user, o);
     Error e = finish_part(f, idx.data(), F.prec_mask, F);
     if (e.st != MBF_OK) return e;
@@ -601,7 +641,12 @@ Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, m
     const int64_t c1 = w1[i] - half, c2 = w2[i] - half;
     if (c1 >= -a_c && c1 < a_c && c2 >= -a_c && c2 < a_c) cen_idx.push_back(i);
   }
-  if (!cen_idx.empty()) {
+  if (!cen_idx.empty() && dev) {
+    Error e = build_center_device(DK, cen_idx, F.prec_mask, F);
+    if (e.st != MBF_OK) return e;
+    F.nnz += nx * (int64_t)cen_idx.size();
+    for (auto& p : F.center) F.device_bytes += p.bytes;
+  } else if (!cen_idx.empty()) {
     std::vector<int64_t> rows(nx);
     std::iota(rows.begin(), rows.end(), 0);
     std::vector<cd> KC((size_t)(nx * (int64_t)cen_idx.size()));

@@ -166,6 +166,24 @@ mbf_status mbf_multiscale_assemble(int32_t nparts, mbf_factor* parts, const int6
     *out = nullptr;
     const int64_t nx = parts[0]->dev.nx;
     prec_mask &= (1u << kNumPrec) - 1;
+    // Every Omega index of a part and of the center must name a point of
+    // Omega: the apply gathers and scatters through them.
+    for (int32_t t = 0; t < nparts; ++t) {
+      if (part_n[t] < 0 || (part_n[t] > 0 && !part_idx[t])) {
+        release();
+        return fail(MBF_ERR_INVALID_ARG, "invalid multiscale part index list");
+      }
+      for (int64_t k = 0; k < part_n[t]; ++k)
+        if (part_idx[t][k] < 0 || part_idx[t][k] >= nxi) {
+          release();
+          return fail(MBF_ERR_INVALID_ARG, "multiscale part index outside [0, nxi)");
+        }
+    }
+    for (int64_t k = 0; k < n_center; ++k)
+      if (center_idx[k] < 0 || center_idx[k] >= nxi) {
+        release();
+        return fail(MBF_ERR_INVALID_ARG, "center index outside [0, nxi)");
+      }
     for (int32_t t = 0; t < nparts; ++t) {
       if (!parts[t] || parts[t]->dev.parts.size() != 1 || parts[t]->dev.nx != nx ||
           parts[t]->dev.nxi != part_n[t] || (parts[t]->dev.prec_mask & prec_mask) != prec_mask) {

@@ -121,12 +121,11 @@ Error upload_real(int p, const double* src, size_t count, void** dst, size_t& by
 
 }  // namespace
 
-Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mask, DevPart& P) {
-  const int L = f.L;
-  const Tree& xt = f.xt;
-  const Tree& ot = f.ot;
+Error layout_part(const Tree& xt, const Tree& ot, int L, int m, const std::vector<std::vector<int32_t>>& rank,
+                  const int64_t* idx_map, DevPart& P, std::vector<int64_t>* blk_off) {
+  auto pair = [&](int s, int32_t ia, int32_t ib) { return (int64_t)ia * ot.nn(L - s) + ib; };
   P.L = L;
-  P.m = f.m;
+  P.m = m;
   P.nx = xt.npts;
   P.nxi = ot.npts;
   std::vector<std::vector<int64_t>> roff(L + 1);
@@ -134,10 +133,12 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
   P.ld.assign(L + 1, 0);
   P.max_rank.assign(L + 1, 0);
   for (int s = 0; s <= L; ++s) {
-    const auto& rk = f.rank[s];
+    const auto& rk = rank[s];
+    if ((int64_t)rk.size() != (int64_t)xt.nn(s) * ot.nn(L - s)) return {MBF_ERR_INVALID_ARG, "rank table size"};
     roff[s].resize(rk.size() + 1);
     int64_t acc = 0;
     for (size_t p = 0; p < rk.size(); ++p) {
+      if (rk[p] < 0) return {MBF_ERR_INVALID_ARG, "negative rank"};
       roff[s][p] = acc;
       acc += rk[p];
       P.max_rank[s] = std::max(P.max_rank[s], rk[p]);
@@ -147,46 +148,48 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
     P.rows[s] = acc;
     P.ld[s] = std::max<int64_t>(4, (acc + 3) / 4 * 4);
   }
-  // Stage block descriptors.
+  // Stage block descriptors; blocks are stored in block order, so a block's
+  // offset inside its stage is the sum of M * K over the blocks before it.
   std::vector<BlockDesc> blks;
   P.nblk.assign(L, 0);
   P.blk_first.assign(L, 0);
   P.w_stage_off.assign(L, 0);
   P.max_M.assign(L, 0);
   P.max_K.assign(L, 0);
+  if (blk_off) blk_off->clear();
   int64_t woff = 0;
   for (int s = 0; s < L; ++s) {
     const int lo = L - s - 1;
     P.blk_first[s] = (int64_t)blks.size();
     P.w_stage_off[s] = woff;
-    int64_t b = 0;
+    int64_t b = 0, soff = 0;
     for (int32_t ia = 0; ia < xt.nn(s); ++ia)
       for (int32_t ibp = 0; ibp < ot.nn(lo); ++ibp, ++b) {
         BlockDesc d{};
-        d.w_off = woff + f.Woff[s][b];
+        d.w_off = soff;
         const int32_t ib0 = ot.cfirst[lo][ibp], ib1 = ot.cfirst[lo][ibp + 1];
-        d.in_row = (int32_t)roff[s][f.pair(s, ia, ib0)];
-        d.K = (int32_t)(roff[s][f.pair(s, ia, ib1 - 1) + 1] - d.in_row);
+        d.in_row = (int32_t)roff[s][pair(s, ia, ib0)];
+        d.K = (int32_t)(roff[s][pair(s, ia, ib1 - 1) + 1] - d.in_row);
         int32_t M = 0, t = 0;
         for (int32_t it = xt.cfirst[s][ia]; it < xt.cfirst[s][ia + 1]; ++it, ++t) {
-          const int64_t p = f.pair(s + 1, it, ibp);
+          const int64_t p = pair(s + 1, it, ibp);
           d.ms[t] = M;
           d.orow[t] = (int32_t)roff[s + 1][p];
-          M += f.rank[s + 1][p];
+          M += rank[s + 1][p];
         }
         for (; t < 4; ++t) {
           d.ms[t] = M;
           d.orow[t] = 0;
         }
         d.M = M;
-        if ((int64_t)d.M * d.K != f.Woff[s][b + 1] - f.Woff[s][b])
-          return {MBF_ERR_INVALID_ARG, "block size mismatch at stage " + std::to_string(s)};
         P.max_M[s] = std::max(P.max_M[s], d.M);
         P.max_K[s] = std::max(P.max_K[s], d.K);
+        if (blk_off) blk_off->push_back(soff);
+        soff += (int64_t)d.M * d.K;
         blks.push_back(d);
       }
     P.nblk[s] = b;
-    woff += (int64_t)f.W[s].size();
+    woff += soff;
   }
   P.w_elems = woff;
   // Leaves.
@@ -197,10 +200,8 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
     d.f_off = fo;
     d.p_off = (int32_t)ot.off[L][ib];
     d.np = (int32_t)ot.size(L, ib);
-    d.r = f.rank[0][f.pair(0, 0, ib)];
-    d.row = (int32_t)roff[0][f.pair(0, 0, ib)];
-    if ((int64_t)d.np * d.r != (int64_t)f.V0[ib].size())
-      return {MBF_ERR_INVALID_ARG, "Omega leaf factor size mismatch"};
+    d.r = rank[0][pair(0, 0, ib)];
+    d.row = (int32_t)roff[0][pair(0, 0, ib)];
     fo += (int64_t)d.np * d.r;
     P.max_vnp = std::max(P.max_vnp, d.np);
     P.max_vr = std::max(P.max_vr, d.r);
@@ -213,10 +214,8 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
     d.f_off = fo;
     d.p_off = (int32_t)xt.off[L][ia];
     d.np = (int32_t)xt.size(L, ia);
-    d.r = f.rank[L][f.pair(L, ia, 0)];
-    d.row = (int32_t)roff[L][f.pair(L, ia, 0)];
-    if ((int64_t)d.np * d.r != (int64_t)f.UL[ia].size())
-      return {MBF_ERR_INVALID_ARG, "X leaf factor size mismatch"};
+    d.r = rank[L][pair(L, ia, 0)];
+    d.row = (int32_t)roff[L][pair(L, ia, 0)];
     fo += (int64_t)d.np * d.r;
     P.max_unp = std::max(P.max_unp, d.np);
     P.max_ur = std::max(P.max_ur, d.r);
@@ -225,9 +224,8 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
   P.u_elems = fo;
   P.n_vleaf = (int32_t)vl.size();
   P.n_uleaf = (int32_t)ul.size();
-  if ((int64_t)f.S.size() != P.rows[f.m]) return {MBF_ERR_INVALID_ARG, "middle scaling size mismatch"};
-  P.s_elems = (int64_t)f.S.size();
-  P.nnz = host_nnz(f);
+  P.s_elems = P.rows[m];
+  P.nnz = P.w_elems + P.v_elems + P.u_elems + P.s_elems;
 
   std::vector<int32_t> vidx(ot.npts), uidx(xt.npts);
   for (int64_t i = 0; i < ot.npts; ++i) vidx[i] = (int32_t)(idx_map ? idx_map[ot.perm[i]] : ot.perm[i]);
@@ -239,6 +237,25 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
   MBF_TRY(dev_alloc_copy((void**)&P.d_uleaf, ul.data(), ul.size(), meta));
   MBF_TRY(dev_alloc_copy((void**)&P.d_vidx, vidx.data(), vidx.size(), meta));
   MBF_TRY(dev_alloc_copy((void**)&P.d_uidx, uidx.data(), uidx.size(), meta));
+  return {MBF_OK, ""};
+}
+
+Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mask, DevPart& P) {
+  const int L = f.L;
+  MBF_TRY(layout_part(f.xt, f.ot, L, f.m, f.rank, idx_map, P, nullptr));
+  for (int s = 0; s < L; ++s) {
+    const int64_t e = (s + 1 < L ? P.w_stage_off[s + 1] : P.w_elems) - P.w_stage_off[s];
+    if (e != (int64_t)f.W[s].size()) return {MBF_ERR_INVALID_ARG, "block size mismatch at stage " + std::to_string(s)};
+  }
+  for (int32_t ib = 0; ib < f.ot.nn(L); ++ib)
+    if (f.ot.size(L, ib) * f.rank[0][f.pair(0, 0, ib)] != (int64_t)f.V0[ib].size())
+      return {MBF_ERR_INVALID_ARG, "Omega leaf factor size mismatch"};
+  for (int32_t ia = 0; ia < f.xt.nn(L); ++ia)
+    if (f.xt.size(L, ia) * f.rank[L][f.pair(L, ia, 0)] != (int64_t)f.UL[ia].size())
+      return {MBF_ERR_INVALID_ARG, "X leaf factor size mismatch"};
+  if ((int64_t)f.S.size() != P.rows[f.m]) return {MBF_ERR_INVALID_ARG, "middle scaling size mismatch"};
+  P.nnz = host_nnz(f);
+  const int64_t woff = P.w_elems;
 
   // Upload stage by stage (no host copy of the whole factorization).
   for (int p = 0; p < kNumPrec; ++p) {
@@ -247,16 +264,19 @@ Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mas
     d.present = true;
     const int leafp = (p == MBF_C128) ? MBF_C128 : MBF_C64;
     const size_t esz = (p == MBF_C128) ? 16 : 8;
+    d.Wst.assign(L, nullptr);
     if (woff > 0) {
-      hipError_t e = hipMalloc(&d.W, (size_t)woff * esz);
-      if (e != hipSuccess) {
-        d.W = nullptr;
+      void* W = nullptr;
+      hipError_t e = hipMalloc(&W, (size_t)woff * esz);
+      if (e != hipSuccess)
         return {e == hipErrorOutOfMemory ? MBF_ERR_OOM : MBF_ERR_HIP,
                 std::string("hipMalloc (stage blocks) failed: ") + hipGetErrorString(e)};
-      }
+      d.Walloc.push_back(W);
       d.bytes += (size_t)woff * esz;
-      for (int s = 0; s < L; ++s)
-        MBF_TRY(copy_blocks(p, f.W[s].data(), f.W[s].size(), (char*)d.W + (size_t)P.w_stage_off[s] * esz));
+      for (int s = 0; s < L; ++s) {
+        d.Wst[s] = (char*)W + (size_t)P.w_stage_off[s] * esz;
+        MBF_TRY(copy_blocks(p, f.W[s].data(), f.W[s].size(), d.Wst[s]));
+      }
     }
     std::vector<cd> tmp;
     tmp.reserve((size_t)std::max(P.v_elems, P.u_elems));
@@ -286,7 +306,7 @@ Error upload_center(DevFactor& F, const std::vector<cd>& KC, const std::vector<i
 }
 
 static void free_prec(PrecData& d) {
-  (void)hipFree(d.W);
+  for (void* w : d.Walloc) (void)hipFree(w);
   (void)hipFree(d.V0);
   (void)hipFree(d.UL);
   (void)hipFree(d.S);

@@ -21,7 +21,7 @@
 namespace mbf {
 
 struct BlockDesc {
-  int64_t w_off;   // element offset of the block's M x K matrix
+  int64_t w_off;   // element offset of the block's M x K matrix from the start of its stage
   int32_t M, K;    // output rows / input rows (forward direction)
   int32_t in_row;  // first stage-s row of the contiguous input side
   int32_t ms[4];   // start of output group t inside [0, M); unused groups = M
@@ -43,7 +43,12 @@ constexpr int kNumPrec = 3;
 
 struct PrecData {
   bool present = false;
-  void* W = nullptr;      // all stage blocks (element type depends on precision)
+  // Stage blocks (element type depends on precision): Wst[s] is the start of
+  // stage s; block descriptors address their matrix relative to it.  The
+  // stages live in the allocations listed in Walloc (one for all stages, or
+  // one per stage when a builder writes stages as they complete).
+  std::vector<void*> Wst;
+  std::vector<void*> Walloc;
   void* V0 = nullptr;     // Omega-leaf factors
   void* UL = nullptr;     // X-leaf factors
   void* S = nullptr;      // middle scaling, real, state-h rows
@@ -91,6 +96,12 @@ struct DevFactor {
   mutable Profiler prof;
 };
 
+// Layout of a part from its trees and ranks alone (Section 2.5 bookkeeping):
+// state rows, stage block and leaf descriptors, and the point-index arrays,
+// uploaded to the device; no factor data.  blk_off (optional) receives the
+// offset of every block inside its stage, in block order.
+Error layout_part(const Tree& xt, const Tree& ot, int L, int m, const std::vector<std::vector<int32_t>>& rank,
+                  const int64_t* idx_map, DevPart& P, std::vector<int64_t>* blk_off);
 // Upload a host factorization as one part.  idx_map (optional, nxi
 // entries) maps the part's Omega column order to the caller's order.
 Error upload_part(const HostFactor& f, const int64_t* idx_map, uint32_t prec_mask, DevPart& out);

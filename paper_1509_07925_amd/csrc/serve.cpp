@@ -14,6 +14,15 @@
 // Batches on different slots overlap on the device.  Completion is observed
 // by polling the events; a request's latency is completion - submission on
 // the host clock.
+//
+// Admission never fails a request that fits alone: when a batch of several
+// requests exceeds the pool, trailing requests are left in the queue until
+// the batch fits; only a request whose own staging and workspace exceed the
+// whole budget completes with MBF_ERR_OOM.  A batch whose apply cannot be
+// enqueued completes each of its requests with that error.  Records of
+// completed requests are kept until polled (at most kMaxRecords; the oldest
+// unpolled ones are dropped beyond that); the latency statistics keep the
+// last kMaxLatencies completions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,8 +55,17 @@ struct Request {
   int64_t ldg;
   void* u;
   int64_t ldu;
+  hipEvent_t ready;  // g is complete once this event has completed (null: already complete)
   clk::time_point t_submit;
 };
+
+struct Record {
+  double latency_us;
+  mbf_status st;
+};
+
+constexpr size_t kMaxRecords = (size_t)1 << 20;
+constexpr size_t kMaxLatencies = (size_t)1 << 20;
 
 // First-fit allocator over one device allocation (offsets 256-byte aligned).
 struct Pool {
@@ -96,6 +114,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  mbf_status st = MBF_OK;  // status given to every request of the batch
   std::vector<Request> reqs;
   size_t off = 0, bytes = 0;
 };
@@ -110,8 +129,10 @@ struct Server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request> queue;
-  std::map<uint64_t, double> done_latency_us;  // completed requests
-  std::vector<double> all_latency_us;
+  std::map<uint64_t, Record> records;  // completed, not yet polled
+  std::vector<double> latencies;       // ring of the last kMaxLatencies completions
+  size_t lat_next = 0;
+  uint64_t lat_count = 0;
   std::atomic<uint64_t> next_id{1};
   bool stop = false;
   std::string error;
@@ -124,6 +145,22 @@ struct Server {
     const size_t es = r.prec == MBF_C128 ? 16 : 8;
     const size_t io = (size_t)(F.nxi + F.nx) * (size_t)nrhs * es;
     return (io + 255) / 256 * 256 + workspace_bytes(F, r.prec, nrhs);
+  }
+
+  void complete(const Request& r, mbf_status st, clk::time_point now) {
+    const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
+    if (records.size() >= kMaxRecords) records.erase(records.begin());
+    records[r.id] = Record{us, st};
+    if (st != MBF_OK) return;
+    if (latencies.size() < kMaxLatencies) {
+      latencies.push_back(us);
+    } else {
+      latencies[lat_next] = us;
+      lat_next = (lat_next + 1) % kMaxLatencies;
+    }
+    ++lat_count;
+    rhs_done += r.nrhs;
+    ++requests_done;
   }
 
   // Launch one batch on slot s; called with mu held.
@@ -139,11 +176,16 @@ struct Server {
       take.push_back(i);
       cols += r.nrhs;
     }
+    // Leave trailing requests queued until the batch fits the pool.
+    while (take.size() > 1 && batch_bytes(head, cols) > pool.size) {
+      cols -= queue[take.back()].nrhs;
+      take.pop_back();
+    }
     const size_t need = batch_bytes(head, cols);
     if (need > pool.size) {
+      // the head request alone can never fit: it fails, the rest proceed
       error = "request larger than the server memory budget";
-      // fail the head request immediately
-      done_latency_us[head.id] = -1.0;
+      complete(head, MBF_ERR_OOM, clk::now());
       queue.pop_front();
       return true;
     }
@@ -156,22 +198,32 @@ struct Server {
     const size_t io = (size_t)(F.nxi + F.nx) * (size_t)cols * es;
     char* ws = pool.base + off + (io + 255) / 256 * 256;
     s.reqs.clear();
+    s.st = MBF_OK;
     int64_t c0 = 0;
     for (size_t k = 0; k < take.size(); ++k) {
       const Request& r = queue[take[k]];
-      (void)hipMemcpy2DAsync(gb + (size_t)c0 * F.nxi * es, (size_t)F.nxi * es, r.g, (size_t)r.ldg * es,
-                             (size_t)F.nxi * es, (size_t)r.nrhs, hipMemcpyDeviceToDevice, s.stream);
+      if (r.ready && hipStreamWaitEvent(s.stream, r.ready, 0) != hipSuccess) s.st = MBF_ERR_HIP;
+      if (hipMemcpy2DAsync(gb + (size_t)c0 * F.nxi * es, (size_t)F.nxi * es, r.g, (size_t)r.ldg * es,
+                           (size_t)F.nxi * es, (size_t)r.nrhs, hipMemcpyDeviceToDevice, s.stream) != hipSuccess)
+        s.st = MBF_ERR_HIP;
       c0 += r.nrhs;
       s.reqs.push_back(r);
     }
     Error e = launch_apply(F, head.prec, false, cols, gb, F.nxi, ub, F.nx, ws, need - (ws - gb), s.stream);
-    if (e.st != MBF_OK) error = e.msg;
-    c0 = 0;
-    for (const Request& r : s.reqs) {
-      (void)hipMemcpy2DAsync(r.u, (size_t)r.ldu * es, ub + (size_t)c0 * F.nx * es, (size_t)F.nx * es,
-                             (size_t)F.nx * es, (size_t)r.nrhs, hipMemcpyDeviceToDevice, s.stream);
-      c0 += r.nrhs;
+    if (e.st != MBF_OK) {
+      error = e.msg;
+      s.st = e.st;
     }
+    if (s.st == MBF_OK) {
+      c0 = 0;
+      for (const Request& r : s.reqs) {
+        if (hipMemcpy2DAsync(r.u, (size_t)r.ldu * es, ub + (size_t)c0 * F.nx * es, (size_t)F.nx * es,
+                             (size_t)F.nx * es, (size_t)r.nrhs, hipMemcpyDeviceToDevice, s.stream) != hipSuccess)
+          s.st = MBF_ERR_HIP;
+        c0 += r.nrhs;
+      }
+    }
+    if (s.st != MBF_OK && error.empty()) error = "batch enqueue failed";
     (void)hipEventRecord(s.done, s.stream);
     for (size_t k = take.size(); k-- > 0;) queue.erase(queue.begin() + (std::ptrdiff_t)take[k]);
     s.busy = true;
@@ -189,15 +241,14 @@ struct Server {
       int64_t active = 0;
       for (auto& s : slots) {
         if (!s.busy) continue;
-        if (hipEventQuery(s.done) == hipSuccess) {
+        const hipError_t q = hipEventQuery(s.done);
+        if (q != hipErrorNotReady) {
           const auto now = clk::now();
-          for (const Request& r : s.reqs) {
-            const double us = std::chrono::duration<double, std::micro>(now - r.t_submit).count();
-            done_latency_us[r.id] = us;
-            all_latency_us.push_back(us);
-            rhs_done += r.nrhs;
-            ++requests_done;
+          if (q != hipSuccess && s.st == MBF_OK) {
+            s.st = MBF_ERR_HIP;
+            error = std::string("batch failed on the device: ") + hipGetErrorString(q);
           }
+          for (const Request& r : s.reqs) complete(r, s.st, now);
           t_last = now;
           pool.release(s.off, s.bytes);
           s.busy = false;
@@ -267,7 +318,7 @@ mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batc
 }
 
 mbf_status mbf_server_submit(mbf_server srv, mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg,
-                             void* u, int64_t ldu, uint64_t* id) {
+                             void* u, int64_t ldu, void* ready_event, uint64_t* id) {
   Server* s = srv;
   if (!s || !f || !g || !u || !id || nrhs <= 0 || p < 0 || p >= mbf::kNumPrec) {
     mbf::set_error("invalid submit arguments");
@@ -281,7 +332,7 @@ mbf_status mbf_server_submit(mbf_server srv, mbf_factor f, mbf_prec p, int64_t n
     mbf::set_error("leading dimension too small");
     return MBF_ERR_INVALID_ARG;
   }
-  mbf::Request r{s->next_id++, f, (int)p, nrhs, g, ldg, u, ldu, mbf::clk::now()};
+  mbf::Request r{s->next_id++, f, (int)p, nrhs, g, ldg, u, ldu, (hipEvent_t)ready_event, mbf::clk::now()};
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
@@ -303,13 +354,27 @@ mbf_status mbf_server_poll(mbf_server srv, uint64_t id, int32_t* done, double* l
     return MBF_ERR_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->done_latency_us.find(id);
-  *done = it != s->done_latency_us.end();
-  if (*done && it->second < 0) {
-    mbf::set_error(s->error);
-    return MBF_ERR_OOM;
+  *done = 0;
+  if (latency_us) *latency_us = 0.0;
+  auto it = s->records.find(id);
+  if (it == s->records.end()) {
+    // still queued or in flight, or never issued / already reported
+    bool pending = false;
+    for (const auto& r : s->queue) pending = pending || r.id == id;
+    for (const auto& sl : s->slots)
+      for (const auto& r : sl.reqs) pending = pending || (sl.busy && r.id == id);
+    if (pending) return MBF_OK;
+    mbf::set_error("unknown request id (never issued, or its completion was already reported)");
+    return MBF_ERR_INVALID_ARG;
   }
-  if (latency_us) *latency_us = *done ? it->second : 0.0;
+  const mbf::Record rec = it->second;
+  s->records.erase(it);
+  *done = 1;
+  if (latency_us) *latency_us = rec.latency_us;
+  if (rec.st != MBF_OK) {
+    mbf::set_error(s->error.empty() ? "request failed" : s->error);
+    return rec.st;
+  }
   return MBF_OK;
 }
 
@@ -335,7 +400,7 @@ mbf_status mbf_server_stats(mbf_server srv, mbf_server_stats_t* out) {
   if (!s || !out) return MBF_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(s->mu);
   std::memset(out, 0, sizeof(*out));
-  std::vector<double> v = s->all_latency_us;
+  std::vector<double> v = s->latencies;
   std::sort(v.begin(), v.end());
   auto pct = [&](double q) { return v.empty() ? 0.0 : v[std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5))]; };
   out->requests = s->requests_done;

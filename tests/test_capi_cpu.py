@@ -98,3 +98,141 @@ def test_load_rejects_missing_and_corrupted_files(tmp_path):
     with pytest.raises(mbf.MBFError) as e:
         mbf.Factor.load(str(wrongver))
     assert "version" in str(e.value)
+
+
+def test_failing_entry_callback_reports_callback_error_and_leaks_no_handle():
+    """A Python entry callback that raises aborts the host build with
+    MBF_ERR_CALLBACK; the output handle stays null."""
+    lib = mbf.lib()
+    n = 8
+    x = np.ascontiguousarray(W.grid_x_integer(n))
+    xi = np.ascontiguousarray(W.grid_omega(n))
+    calls = []
+
+    def bad(rows, cols):
+        calls.append(rows.size)
+        raise RuntimeError("entry evaluation failed")
+
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.build(x, xi, n, kernel=bad, tol=1e-6, leaf_side=2, builder="host")
+    assert e.value.status == -3
+    assert calls, "the callback was never reached"
+    # the same failure through the raw ABI: the handle is left null
+    cb = mbf.ENTRY_CB(lambda user, m, rows, k, cols, out: 7)
+    o = mbf._Opts(1e-6, 64, 0, 2, n, 0, 16, 10, 0, 2, 1, 0, 0)
+    h = ctypes.c_void_p(12345)
+    st = lib.mbf_build(2, x.shape[0], x.ctypes.data, xi.shape[0], xi.ctypes.data, cb, None, ctypes.byref(o), None,
+                       ctypes.byref(h))
+    assert st == -3
+    assert not h.value
+    assert "callback" in lib.mbf_last_error().decode()
+
+
+def test_device_builder_refuses_what_it_cannot_evaluate():
+    """The device builder evaluates the ready-made kernels only, at tol >= 1e-7;
+    other requests fail with MBF_ERR_UNSUPPORTED before any device work."""
+    n = 8
+    x, xi = W.grid_x_integer(n), W.grid_omega(n)
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.build(x, xi, n, kernel=lambda r, c: np.ones((r.size, c.size)), builder="device")
+    assert e.value.status == -5
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.build(x, xi, n, kernel="dft", tol=1e-9, builder="device")
+    assert e.value.status == -5
+    with pytest.raises(KeyError):
+        mbf.Factor.build(x, xi, n, builder="somewhere")
+
+
+# ---------------------------------------------------------------- factor files
+# A factor file written by hand in the documented layout (csrc/io.cpp): one
+# part of depth 0 over one X point and one Omega point, rank 1, complex64.
+# Every corrupted variant must be refused with MBF_ERR_IO while parsing, i.e.
+# before any device memory is touched.
+
+def _hash(stream):
+    h = 0x84222325cbf29ce4
+    mask = (1 << 64) - 1
+    pad = stream + bytes((-len(stream)) % 8)
+    for i in range(0, len(pad), 8):
+        w = int.from_bytes(pad[i:i + 8], "little")
+        h = ((h ^ w) * 0x100000001b3) & mask
+        h = ((h << 29) | (h >> 35)) & mask
+    return h
+
+
+def _tiny_factor_file(**bad):
+    import struct
+    f = dict(L=0, m=0, nvl=1, nul=1, mvnp=1, munp=1, mvr=1, mur=1, rows=1, ld=4, vleaf=(0, 0, 1, 1, 0),
+             uleaf=(0, 0, 1, 1, 0), vidx=0, uidx=0, s_elems=1, nparts=1)
+    f.update(bad)
+
+    def vec(fmt, vals):
+        return struct.pack("<Q", len(vals)) + b"".join(struct.pack("<" + fmt, v) for v in vals)
+
+    p = b"MBFFACT1" + struct.pack("<II", 2, 1 << 1) + struct.pack("<qqq", 1, 1, 0) + struct.pack("<I", f["nparts"])
+    p += struct.pack("<8i", f["L"], f["m"], f["nvl"], f["nul"], f["mvnp"], f["munp"], f["mvr"], f["mur"])
+    p += struct.pack("<7q", 1, 1, 3, 0, 1, 1, f["s_elems"])
+    p += vec("q", [f["rows"]]) + vec("q", [f["ld"]]) + vec("q", []) + vec("q", []) + vec("q", [])
+    p += vec("i", [1]) + vec("i", []) + vec("i", [])
+    p += struct.pack("<q4i", *f["vleaf"]) + struct.pack("<q4i", *f["uleaf"])
+    p += struct.pack("<i", f["vidx"]) + struct.pack("<i", f["uidx"])
+    p += struct.pack("<ff", 1.0, 0.0) + struct.pack("<ff", 1.0, 0.0) + struct.pack("<f", 1.0)
+    return p + b"MBFEND01" + struct.pack("<QQ", len(p), _hash(p))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ld=0),                      # leading dimension below the state rows
+    dict(rows=-1),                   # negative state rows
+    dict(vleaf=(5, 0, 1, 1, 0)),     # leaf factor outside the leaf array
+    dict(uleaf=(0, 3, 1, 1, 0)),     # leaf points outside the point-index array
+    dict(vleaf=(0, 0, 1, 1, 2)),     # leaf state rows outside stage 0
+    dict(vidx=7),                    # Omega point index outside [0, nxi)
+    dict(uidx=-2),                   # X point index outside [0, nx)
+    dict(s_elems=2),                 # middle scaling longer than the middle state
+    dict(mvnp=4),                    # leaf maxima that disagree with the leaves
+    dict(m=3),                       # middle level deeper than the tree
+    dict(nparts=0),                  # no parts
+])
+def test_load_refuses_inconsistent_factor_files(tmp_path, bad):
+    path = tmp_path / "bad.mbf"
+    path.write_bytes(_tiny_factor_file(**bad))
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.load(str(path))
+    assert e.value.status == -7, str(e.value)
+
+
+def test_hand_written_factor_file_parses(tmp_path):
+    """The well-formed tiny file passes every check on the host; without a GPU
+    the load then stops at the first device allocation (not an I/O error)."""
+    path = tmp_path / "ok.mbf"
+    path.write_bytes(_tiny_factor_file())
+    try:
+        torch = __import__("torch")
+        has_gpu = torch.cuda.is_available()
+    except ImportError:
+        has_gpu = False
+    if has_gpu:
+        F = mbf.Factor.load(str(path))
+        assert F.info().nnz == 3
+    else:
+        with pytest.raises(mbf.MBFError) as e:
+            mbf.Factor.load(str(path))
+        assert e.value.status != -7, str(e.value)
+
+
+def test_column_bar_catches_one_bad_column():
+    """The GPU parity check flags a single column 10x over the bar among
+    300 correct ones (a whole-block norm would not)."""
+    from tests.bars import assert_columns_close
+    rng = np.random.default_rng(0)
+    ref = rng.standard_normal((500, 300)) + 1j * rng.standard_normal((500, 300))
+    got = ref * (1 + 1e-8)
+    assert_columns_close(got, ref, 1e-6)
+    got[:, 17] = ref[:, 17] * (1 + 1e-5)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-6  # the block norm misses it
+    with pytest.raises(AssertionError):
+        assert_columns_close(got, ref, 1e-6)
+    got = ref.copy()
+    got[3, 5] += 1e-3 * np.abs(ref[:, 5]).max()  # one wrong entry
+    with pytest.raises(AssertionError):
+        assert_columns_close(got, ref, 1e-6)

@@ -2,11 +2,14 @@
 
 Arithmetic parity: the oracle builds a factorization, the library imports
 the same factors (mbf_import), and both apply them to the same seeded
-vectors.  Bars (relative l2 error over all outputs):
+vectors.  Bars, checked for every column (relative l2 error) and every
+entry (error relative to its column's largest entry), tests/bars.py:
   complex128 path  <= 1e-12
   complex64 path   <= 1e-6    (FP32 apply vs FP64 oracle)
-End-to-end: the library's own build (mbf_build) applied on the GPU against
-the plain definition (FFT closed form / direct sum), within 10 x tol.
+  split BF16       <= 1e-4
+End-to-end: the library's own build (mbf_build, host and device builders)
+applied on the GPU against the plain definition (FFT closed form / direct
+sum), within 10 x tol.
 """
 
 import numpy as np
@@ -14,6 +17,7 @@ import pytest
 
 import mbf_workloads as W
 from oracle import butterfly, direct, kernels
+from tests.bars import assert_columns_close
 from tests.factor_io import to_import
 
 torch = pytest.importorskip("torch")
@@ -58,10 +62,10 @@ def _import(bf, precs):
 def _check_both(F, bf, nx, nxi, nrhs, prec, seed=0):
     g = W.rhs(nxi, nrhs, seed=seed)
     u = _from_gpu(F.apply(_to_gpu(g, prec), prec=prec))
-    assert direct.rel_err(u, bf.apply(g)) <= BAR[prec]
+    assert_columns_close(u, bf.apply(g), BAR[prec], "apply %s" % prec)
     h = W.rhs(nx, nrhs, seed=seed + 1)
     v = _from_gpu(F.apply_adjoint(_to_gpu(h, prec), prec=prec))
-    assert direct.rel_err(v, bf.adjoint(h)) <= BAR[prec]
+    assert_columns_close(v, bf.adjoint(h), BAR[prec], "adjoint %s" % prec)
     return u, v
 
 
@@ -76,7 +80,8 @@ def test_dft_small_import_parity(prec, nrhs):
 
 @pytest.mark.parametrize("leaf,tol", [(1, 1e-14), (4, 1e-14), (2, 1e-5)])
 def test_dft_depth_variants_parity(leaf, tol):
-    # odd and even depth, middle level 0 and > 0, full rank and truncated
+    # depth L = 4, 2, 3 (even and odd, middle level 2, 1, 1), full rank and
+    # truncated; middle level 0 is covered by test_wide_leaves_middle_level_zero
     n = 16
     bf = _dft_oracle(n, leaf, tol)
     F = _import(bf, ["c128", "c64"])
@@ -140,14 +145,14 @@ def test_batch_columns_equal_solo_apply(prec, nrhs):
     np.testing.assert_array_equal(up, ub[:, perm])
     for j in (0, nrhs // 2, nrhs - 1):
         uj = _from_gpu(F.apply(_to_gpu(g[:, j:j + 1], prec), prec=prec))
-        assert direct.rel_err(uj, ub[:, j:j + 1]) <= BAR[prec]
+        assert_columns_close(uj, ub[:, j:j + 1], BAR[prec], "column %d alone" % j)
 
 
 @pytest.mark.parametrize("n,leaf,tol", [(32, 2, 1e-6), (64, 4, 1e-6)])
 def test_library_build_dft_end_to_end(n, leaf, tol):
     mbf = _mbf()
     x, xi = W.grid_x_integer(n), W.grid_omega(n)
-    F = mbf.Factor.build(x, xi, n, kernel="dft", tol=tol, leaf_side=leaf, precs=["c64", "c128"])
+    F = mbf.Factor.build(x, xi, n, kernel="dft", tol=tol, leaf_side=leaf, precs=["c64", "c128"], builder="host")
     g = W.rhs(n * n, 8, seed=5)
     ref = direct.dft_fft(n, g)
     u = _from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128"))
@@ -169,7 +174,7 @@ def test_library_build_fio_splits_end_to_end(split):
     n = 64
     x, xi = W.grid_x_unit(n), W.grid_omega(n)
     kw = dict(depth=4) if split == "polar" else dict(leaf_side=4)
-    F = mbf.Factor.build(x, xi, n, kernel="fio", tol=1e-6, split=split, precs=["c64"], **kw)
+    F = mbf.Factor.build(x, xi, n, kernel="fio", tol=1e-6, split=split, precs=["c64"], builder="host", **kw)
     g = W.rhs(n * n, 4, seed=7)
     rows = W.sample_rows(n * n, 256, seed=0)
     ref = direct.direct_rows(kernels.fio_radon(n), x, xi, g, rows)
@@ -290,3 +295,118 @@ def test_autotune_choices_persist_in_tune_file(tmp_path, monkeypatch):
         assert 0 <= v < (11 if prec_id == 1 else 7)
     _check_both(F, bf, n * n, n * n, 200, "c64", seed=3)
     _check_both(F, bf, n * n, n * n, 200, "bf16x3", seed=4)
+
+
+@pytest.mark.parametrize("n,leaf", [(32, 32), (64, 32)])
+@pytest.mark.timeout(900)  # the FP64 oracle takes exact SVDs of 4096 x 1024 blocks at n = 64
+def test_wide_leaves_middle_level_zero(n, leaf):
+    """Leaves of 1024 points (the leaf projection of more than 256 points,
+    forward on the Omega side and adjoint on the X side) and middle level
+    h = 0 (the middle scaling S applied inside the leaf projection): the 2D
+    DFT with depth 0 (n = 32, no stages, h = L = 0) and depth 1 (n = 64, one
+    G-side stage of 4096 x 4096 blocks, h = 0)."""
+    import threadpoolctl
+    with threadpoolctl.threadpool_limits(16):
+        bf = _dft_oracle(n, leaf, 1e-10)
+    assert bf.m == 0 and bf.L == int(np.log2(n // leaf))
+    assert max(len(bf.xt.points(bf.L, int(a))) for a in bf.xt.nodes[bf.L]) == 1024
+    F = _import(bf, ["c128", "c64"])
+    for prec, nrhs in (("c128", 3), ("c64", 5), ("c64", 17)):
+        _check_both(F, bf, n * n, n * n, nrhs, prec, seed=nrhs)
+    # the factorization is the DFT itself (full rank): FFT closed form
+    g = W.rhs(n * n, 2, seed=7)
+    assert direct.rel_err(_from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128")), direct.dft_fft(n, g)) < 1e-12
+
+
+@pytest.mark.parametrize("n,L,want", [(2, 1, 28), (4, 1, 400)])
+def test_library_nnz_equals_hand_count(n, L, want):
+    """mbf_info's nnz of imported factors equals the hand count of the
+    oracle pin (Section 2.5: apply cost = nonzeros)."""
+    bf = _dft_oracle(n, n >> L, 1e-14)
+    assert bf.nnz() == want
+    F = _import(bf, ["c64"])
+    assert F.info().nnz == want
+
+
+@pytest.mark.parametrize("n,leaf", [(64, 4), (128, 4)])
+def test_device_build_dft_against_fft(n, leaf):
+    """Factors built on the GPU (mbf_build, device builder) applied on the GPU
+    against the FFT closed form, forward and adjoint, within 10 x tol."""
+    mbf = _mbf()
+    tol = 1e-6
+    x, xi = W.grid_x_integer(n), W.grid_omega(n)
+    F = mbf.Factor.build(x, xi, n, kernel="dft", tol=tol, leaf_side=leaf, precs=["c64", "c128"], builder="device")
+    g = W.rhs(n * n, 6, seed=31)
+    u = _from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128"))
+    assert_columns_close(u, direct.dft_fft(n, g), 10 * tol, "device build, FP64 apply vs FFT")
+    u32 = _from_gpu(F.apply(_to_gpu(g, "c64")))
+    assert_columns_close(u32, direct.dft_fft(n, g), 10 * tol + 1e-6, "device build, FP32 apply vs FFT")
+    h = W.rhs(n * n, 6, seed=32)
+    v = _from_gpu(F.apply_adjoint(_to_gpu(h, "c128"), prec="c128"))
+    assert_columns_close(v, direct.dft_fft_adjoint(n, h), 10 * tol, "device build, adjoint vs inverse FFT")
+    assert abs(np.vdot(h, u) - np.vdot(v, g)) <= 1e-10 * abs(np.vdot(h, u))
+
+
+@pytest.mark.parametrize("split", ["polar", "multiscale"])
+def test_device_build_fio_against_direct_sum(split):
+    """Example-1 FIO built on the GPU with the polar and multiscale splits,
+    against the direct sum on 256 sampled rows (Section 3.3's error estimate),
+    within 10 x tol; adjoint identity of the factorized operator."""
+    mbf = _mbf()
+    n, tol = 64, 1e-6
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    kw = dict(depth=4) if split == "polar" else dict(leaf_side=4)
+    F = mbf.Factor.build(x, xi, n, kernel="fio", tol=tol, split=split, precs=["c128"], builder="device", **kw)
+    g = W.rhs(n * n, 4, seed=33)
+    rows = W.sample_rows(n * n, 256, seed=0)
+    ref = direct.direct_rows(kernels.fio_radon(n), x, xi, g, rows)
+    u = _from_gpu(F.apply(_to_gpu(g, "c128"), prec="c128"))
+    assert_columns_close(u[rows], ref, 10 * tol, "device build %s vs direct sum" % split)
+    h = W.rhs(n * n, 4, seed=34)
+    v = _from_gpu(F.apply_adjoint(_to_gpu(h, "c128"), prec="c128"))
+    assert abs(np.vdot(h, u) - np.vdot(v, g)) <= 1e-10 * abs(np.vdot(h, u))
+
+
+def test_device_and_host_builds_agree_on_the_operator():
+    """Both builders take the paper's steps with different linear algebra and
+    random samples: their factors differ, their operators agree within the
+    tolerance (n = 32 DFT, tol 1e-6)."""
+    mbf = _mbf()
+    n = 32
+    x, xi = W.grid_x_integer(n), W.grid_omega(n)
+    Fd = mbf.Factor.build(x, xi, n, kernel="dft", tol=1e-6, leaf_side=2, precs=["c128"], builder="device")
+    Fh = mbf.Factor.build(x, xi, n, kernel="dft", tol=1e-6, leaf_side=2, precs=["c128"], builder="host")
+    assert list(Fd.info().max_rank[:5]) == list(Fh.info().max_rank[:5])
+    g = W.rhs(n * n, 3, seed=35)
+    ud = _from_gpu(Fd.apply(_to_gpu(g, "c128"), prec="c128"))
+    uh = _from_gpu(Fh.apply(_to_gpu(g, "c128"), prec="c128"))
+    assert_columns_close(ud, uh, 1e-5, "device vs host build")
+
+
+def test_saved_file_with_flipped_payload_byte_is_refused(tmp_path):
+    """mbf_load checks the payload checksum: one flipped byte in the factor
+    data fails the load (MBF_ERR_IO) instead of loading wrong factors."""
+    mbf = _mbf()
+    n = 16
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, ["c64"])
+    path = str(tmp_path / "f.mbf")
+    F.save(path)
+    data = bytearray(open(path, "rb").read())
+    data[len(data) - 200] ^= 0x40  # inside the last factor array
+    open(path, "wb").write(bytes(data))
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.load(path)
+    assert e.value.status == -7 and "checksum" in str(e.value)
+
+
+def test_multiscale_assemble_rejects_out_of_range_indices():
+    mbf = _mbf()
+    n = 16
+    bf = _dft_oracle(n, 2, 1e-6)
+    part = _import(bf, ["c64"])
+    idx = np.arange(n * n)
+    idx[5] = n * n + 3  # not a point of Omega
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.multiscale_assemble([part], [idx], n * n, np.zeros(0, np.int64), np.zeros((n * n, 0)), precs=["c64"])
+    assert e.value.status == -1
