@@ -7,12 +7,14 @@ nrhs right-hand sides that are already resident in HBM.  Prints one JSON
 line: RHS/s of the plain FP32 apply, the roofline of the dominant kernel
 (the stage block product) measured with HIP events over the timed steps,
 the relative errors against the FP64 apply of the same factors and against
-the direct sum on sampled rows, the split-BF16 apply on the same factors,
-a short served request mix (p50 / p99 latency), and the CPU oracle's direct
-summation timed on a bounded sample of rows.
+the direct sum on sampled rows, and the CPU oracle (direct FP64 sum and the
+FFT closed form) timed on the host.  Optional legs (split BF16, 16 RHS,
+PCIe-inclusive rate, served request mix) follow while the run stays inside
+its time budget (--deadline seconds from the start); the line lists the
+legs it skipped.  The factors are built on the GPU (FP64 device builder).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
-                       [--save PATH | --load PATH] [--no-cpu-baseline] ...
+                       [--save PATH | --load PATH] [--deadline S] ...
 """
 
 import argparse
@@ -122,17 +124,39 @@ def hbm_roofline(recs):
 
 def measured_traffic(workload, prec):
     """HBM bytes per stage launch from the committed rocprofv3 counter runs
-    (profiles/hbm_traffic_*.json), or None when those counters were taken
-    on another workload / precision or before the stage kernel last changed."""
+    (profiles/hbm_traffic_*.json) with the file they come from, or (None,
+    None) when those counters were taken on another workload / precision or
+    before the stage kernel source last changed (its hash is recorded with
+    the counters)."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1509_07925_amd", "csrc", "stage_mfma.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json"))):
         rec = json.load(open(path))
         if rec.get("workload") == workload and rec.get("prec") == prec and rec.get("kernel_source_sha256_16") == sha:
-            return rec["traffic_bytes_per_launch"]
-    return None
+            return rec["traffic_bytes_per_launch"], {"file": os.path.relpath(path, ROOT), "stage_mfma_sha256_16": sha,
+                                                     "command": rec.get("command")}
+    return None, None
+
+
+class Budget:
+    """Time left before --deadline (seconds since the start of the run)."""
+
+    def __init__(self, deadline):
+        self.t0 = time.time()
+        self.deadline = deadline
+        self.skipped = []
+
+    def left(self):
+        return self.deadline - (time.time() - self.t0)
+
+    def allow(self, name, need_s):
+        if self.left() >= need_s:
+            return True
+        self.skipped.append(name)
+        log("skipping %s (%.0f s left, about %.0f s needed)" % (name, self.left(), need_s))
+        return False
 
 
 def main():
@@ -148,9 +172,13 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--deadline", type=float, default=float(os.environ.get("MBF_BENCH_DEADLINE", "420")),
+                    help="seconds from the start after which optional legs are skipped")
+    ap.add_argument("--builder", default="device", choices=["device", "host"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    budget = Budget(args.deadline)
     if args.copy_calibration:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -165,8 +193,10 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    # Long builds report progress on stderr (at most every 10 s).
+    # Long builds report progress on stderr.
     os.environ.setdefault("MBF_VERBOSE", "1")
+    import signal
+
     import numpy as np
     import torch
 
@@ -181,6 +211,19 @@ def main():
     if cfg.get("fp32_only"):
         args.no_split = args.no_fp64_check = True
     precs = ["c64"] + ([] if args.no_split else ["bf16x3"])
+    out = {"metric": METRIC, "value": None, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+
+    # A SIGTERM (e.g. an outer time limit) prints what has been measured.
+    def on_term(signum, frame):
+        out["terminated"] = "SIGTERM before the run finished"
+        out["skipped_legs"] = budget.skipped
+        print(json.dumps(out), flush=True)
+        os._exit(3)
+
+    signal.signal(signal.SIGTERM, on_term)
+
     t0 = time.time()
     if args.load:
         log("loading", args.load)
@@ -188,10 +231,12 @@ def main():
         built = False
     else:
         all_precs = precs + ([] if args.no_fp64_check else ["c128"])
-        log("building %s (n=%d tol=%g leaf=%d) precs=%s" % (args.config, n, cfg["tol"], cfg["leaf"], all_precs))
+        log("building %s (n=%d tol=%g leaf=%d) precs=%s on the %s" % (args.config, n, cfg["tol"], cfg["leaf"],
+                                                                       all_precs, args.builder))
         F = mbf.Factor.build(x, xi, n, kernel=cfg["kernel"], tol=cfg["tol"], leaf_side=cfg["leaf"],
-                             split=cfg["split"], precs=all_precs, max_rank=4096)
+                             split=cfg["split"], precs=all_precs, max_rank=4096, builder=args.builder)
         built = True
+    torch.cuda.synchronize()
     setup_s = time.time() - t0
     inf = F.info()
     log("setup %.1fs nnz=%.3e depth=%d ranks=%s device GB=%.2f" % (
@@ -209,28 +254,47 @@ def main():
 
     t1 = time.time()
     tuned = F.autotune("c64", nrhs, workspace=ws)
-    if "bf16x3" in precs:
-        tuned += F.autotune("bf16x3", nrhs, workspace=ws)
-    log("autotuned %d stage shapes in %.1fs" % (tuned, time.time() - t1))
+    log("autotuned %d FP32 stage shapes in %.1fs" % (tuned, time.time() - t1))
     total_s, recs = timed_apply(F, g, u, ws, "c64", args.steps, args.warmup)
     ms_per_step = 1e3 * total_s / args.steps
     value = nrhs * args.steps / total_s
     log("FP32: %.1f RHS/s (%.3f ms/step)" % (value, ms_per_step))
-
-    out = {"metric": METRIC, "value": round(value, 2), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": workload_name(cfg),
-                      "kernel": cfg["kernel"], "split": cfg["split"], "n": n, "N": N, "nrhs": nrhs, "tol": cfg["tol"],
-                      "depth": inf.depth, "ranks": list(inf.max_rank[:inf.depth + 1]), "nnz": inf.nnz,
-                      "factor_gb_on_device": round(inf.device_bytes / 1e9, 3),
-                      "setup_s": round(setup_s, 1), "setup": "load" if args.load else "mbf_build (host FP64)"},
-           "roofline": roofline(recs, args.steps, "c64") if nrhs > 32 else hbm_roofline(recs)}
-    out["roofline"]["traffic"] = measured_traffic(out["config"]["workload"], "c64")
+    out.update({"value": round(value, 2), "ms_per_step": round(ms_per_step, 4)})
+    out["config"] = {"workload": workload_name(cfg),
+                     "kernel": cfg["kernel"], "split": cfg["split"], "n": n, "N": N, "nrhs": nrhs, "tol": cfg["tol"],
+                     "depth": inf.depth, "ranks": list(inf.max_rank[:inf.depth + 1]), "nnz": inf.nnz,
+                     "factor_gb_on_device": round(inf.device_bytes / 1e9, 3),
+                     "setup_s": round(setup_s, 1),
+                     "setup": "load" if args.load else "mbf_build (%s FP64)" % args.builder}
+    out["roofline"] = roofline(recs, args.steps, "c64") if nrhs > 32 else hbm_roofline(recs)
+    traffic, src = measured_traffic(out["config"]["workload"], "c64")
+    out["roofline"]["traffic"] = traffic
+    out["roofline"]["traffic_source"] = src
     out["ms_per_step_by_kind"] = breakdown(recs, args.steps)
-
     u32 = u.clone()
-    if cfg.get("adjoint"):
+
+    # error against the FP64 apply of the same factors (required)
+    if built and not args.no_fp64_check:
+        g64 = torch.from_numpy(np.ascontiguousarray(g_host.T)).to(dev, torch.complex128).t()
+        u64 = F.apply(g64, prec="c128")
+        torch.cuda.synchronize()
+        nrm = u64.abs().pow(2).sum().sqrt()
+        out["rel_err_vs_fp64_apply"] = float((u32.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
+        colerr = ((u32.to(torch.complex128) - u64).abs().pow(2).sum(0).sqrt() / u64.abs().pow(2).sum(0).sqrt())
+        out["rel_err_vs_fp64_apply_worst_column"] = float(colerr.max())
+        log("FP32 vs FP64 apply: %.2e (worst column %.2e)" % (out["rel_err_vs_fp64_apply"],
+                                                              out["rel_err_vs_fp64_apply_worst_column"]))
+        del g64
+    else:
+        u64 = None
+
+    u_np = u32.t().contiguous().cpu().numpy().astype(np.complex128).T
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, x, xi, g_host, u_np, out)
+        log("CPU baseline: %s" % out["cpu_baseline"]["sample"])
+
+    # ------------------------------------------------------------ optional legs
+    if cfg.get("adjoint") and budget.allow("adjoint", 30):
         h = torch.empty((nrhs, N), dtype=torch.complex64, device=dev).t()
         h.copy_(g)
         v = torch.empty((nrhs, N), dtype=torch.complex64, device=dev).t()
@@ -241,38 +305,10 @@ def main():
                           "ms_per_step_by_kind": breakdown(a_recs, args.steps)}
         log("FP32 adjoint: %.1f RHS/s" % out["adjoint"]["value"])
         del h, v
-    # few right-hand sides: the 16 x 16 matrix-core stage kernel, bound by reading the blocks from HBM
-    nn = 16
-    if nrhs > nn:
-        g_n, u_n = g[:, :nn], torch.empty((nn, N), dtype=torch.complex64, device=dev).t()
-        n_total, n_recs = timed_apply(F, g_n, u_n, ws, "c64", args.steps, args.warmup)
-        out["narrow_rhs16"] = {"value": round(nn * args.steps / n_total, 2), "unit": "RHS/s",
-                               "ms_per_step": round(1e3 * n_total / args.steps, 4), "nrhs": nn,
-                               "roofline": hbm_roofline(n_recs)}
-        log("FP32 at %d RHS: %.1f RHS/s" % (nn, out["narrow_rhs16"]["value"]))
 
-    # host-resident inputs and outputs: pinned buffers, copies on the same stream (context, not `value`)
-    g_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
-    u_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
-    g_h.copy_(g.t())
-    g_d = torch.empty((nrhs, N), dtype=torch.complex64, device=dev)
-    u_d = torch.empty((nrhs, N), dtype=torch.complex64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pcie_steps = max(2, args.steps // 2)
-    for _ in range(pcie_steps):
-        g_d.copy_(g_h, non_blocking=True)
-        F.apply(g_d.t(), out=u_d.t(), prec="c64", workspace=ws)
-        u_h.copy_(u_d, non_blocking=True)
-    torch.cuda.synchronize()
-    t_p = time.perf_counter() - t0
-    out["pcie_inclusive"] = {"value": round(nrhs * pcie_steps / t_p, 2), "unit": "RHS/s",
-                             "ms_per_step": round(1e3 * t_p / pcie_steps, 4),
-                             "note": "g copied host->device and u device->host (pinned) around each apply"}
-    log("FP32 with host transfers: %.1f RHS/s" % out["pcie_inclusive"]["value"])
-    del g_h, u_h, g_d, u_d
-
-    if not args.no_split:
+    if not args.no_split and budget.allow("split_bf16x3", 60):
+        t1 = time.time()
+        F.autotune("bf16x3", nrhs, workspace=ws)
         u16 = torch.empty_like(u)
         s_total, s_recs = timed_apply(F, g, u16, ws, "bf16x3", args.steps, args.warmup)
         sval = nrhs * args.steps / s_total
@@ -280,158 +316,141 @@ def main():
             u32.to(torch.complex128).abs().pow(2).sum().sqrt()
         out["split_bf16x3"] = {"value": round(sval, 2), "unit": "RHS/s", "ms_per_step": round(1e3 * s_total / args.steps, 4),
                                "dtype": "bf16 hi/lo x3, f32 accumulate", "roofline": roofline(s_recs, args.steps, "bf16x3"),
-                               "rel_diff_vs_fp32_apply": float(d)}
+                               "rel_diff_vs_fp32_apply": float(d), "autotune_s": round(time.time() - t1, 1)}
+        if u64 is not None:
+            out["split_bf16x3"]["rel_err_vs_fp64_apply"] = float(
+                (u16.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / u64.abs().pow(2).sum().sqrt())
         log("BF16x3: %.1f RHS/s" % sval)
         del u16
 
-    if built and not args.no_fp64_check:
-        g64 = torch.from_numpy(np.ascontiguousarray(g_host.T)).to(dev, torch.complex128).t()
-        u64 = F.apply(g64, prec="c128")
-        torch.cuda.synchronize()
-        nrm = u64.abs().pow(2).sum().sqrt()
-        out["rel_err_vs_fp64_apply"] = float((u32.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
-        if "narrow_rhs16" in out:
+    # few right-hand sides: the 16 x 16 matrix-core stage kernel, bound by reading the blocks from HBM
+    nn = 16
+    if nrhs > nn and budget.allow("narrow_rhs16", 30):
+        g_n, u_n = g[:, :nn], torch.empty((nn, N), dtype=torch.complex64, device=dev).t()
+        n_total, n_recs = timed_apply(F, g_n, u_n, ws, "c64", args.steps, args.warmup)
+        out["narrow_rhs16"] = {"value": round(nn * args.steps / n_total, 2), "unit": "RHS/s",
+                               "ms_per_step": round(1e3 * n_total / args.steps, 4), "nrhs": nn,
+                               "roofline": hbm_roofline(n_recs)}
+        if u64 is not None:
             u64n = u64[:, :nn]
             out["narrow_rhs16"]["rel_err_vs_fp64_apply"] = float(
                 (u_n.to(torch.complex128) - u64n).abs().pow(2).sum().sqrt() / u64n.abs().pow(2).sum().sqrt())
-        if "split_bf16x3" in out:
-            u16 = F.apply(g, prec="bf16x3")
-            torch.cuda.synchronize()
-            out["split_bf16x3"]["rel_err_vs_fp64_apply"] = float(
-                (u16.to(torch.complex128) - u64).abs().pow(2).sum().sqrt() / nrm)
-            del u16
-        del g64, u64
-        torch.cuda.empty_cache()
+        log("FP32 at %d RHS: %.1f RHS/s" % (nn, out["narrow_rhs16"]["value"]))
+    del u64
+    torch.cuda.empty_cache()
 
-    if not args.no_serve:
-        out["serving"] = serve_mix(F, N, dev)
-        out["serving_multi"] = serve_multi(args.config, F, N, dev)
-        log("served: p50 %.1f ms p99 %.1f ms; %d factorizations: p50 %.1f ms p99 %.1f ms" % (
-            out["serving"]["p50_ms"], out["serving"]["p99_ms"], out["serving_multi"]["factorizations"],
-            out["serving_multi"]["p50_ms"], out["serving_multi"]["p99_ms"]))
+    # host-resident inputs and outputs: pinned buffers, copies on the same stream (context, not `value`)
+    if budget.allow("pcie_inclusive", 30):
+        g_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
+        u_h = torch.empty((nrhs, N), dtype=torch.complex64, pin_memory=True)
+        g_h.copy_(g.t())
+        g_d = torch.empty((nrhs, N), dtype=torch.complex64, device=dev)
+        u_d = torch.empty((nrhs, N), dtype=torch.complex64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pcie_steps = max(2, args.steps // 2)
+        for _ in range(pcie_steps):
+            g_d.copy_(g_h, non_blocking=True)
+            F.apply(g_d.t(), out=u_d.t(), prec="c64", workspace=ws)
+            u_h.copy_(u_d, non_blocking=True)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t0
+        out["pcie_inclusive"] = {"value": round(nrhs * pcie_steps / t_p, 2), "unit": "RHS/s",
+                                 "ms_per_step": round(1e3 * t_p / pcie_steps, 4),
+                                 "note": "g copied host->device and u device->host (pinned) around each apply"}
+        log("FP32 with host transfers: %.1f RHS/s" % out["pcie_inclusive"]["value"])
+        del g_h, u_h, g_d, u_d
 
-    u_np = u32.t().contiguous().cpu().numpy().astype(np.complex128).T
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, x, xi, g_host, u_np, out)
+    if not args.no_serve and budget.allow("serving", 60):
+        out["serving"] = serve_mix(F, N, dev, budget)
+        log("served at %.0f%% of the measured capacity: p50 %.1f ms p99 %.1f ms" % (
+            100 * out["serving"]["load"], out["serving"]["p50_ms"], out["serving"]["p99_ms"]))
+
+    out["skipped_legs"] = budget.skipped
+    out["wall_s"] = round(time.time() - budget.t0, 1)
     print(json.dumps(out), flush=True)
 
 
-def serve_mix(F, N, dev, nreq=400, seed=0):
-    """Poisson stream of requests with 1..32 RHS on the resident factorization:
-    continuous batching through mbf_server; offered load ~80% of the measured
-    batched throughput."""
+def _serve_run(srv_args, F, N, dev, ins, outs, arrivals):
+    """Submit requests at the given arrival times; per-request latencies (ms)."""
+    import numpy as np
+
+    import paper_1509_07925_amd as mbf
+    srv = mbf.Server(**srv_args)
+    ids = []
+    t_start = time.perf_counter()
+    for i in range(len(ins)):
+        while time.perf_counter() - t_start < arrivals[i]:
+            pass
+        ids.append(srv.submit(F, ins[i], outs[i], ready=False))
+    srv.drain()
+    wall = time.perf_counter() - t_start
+    lat = np.array([srv.poll(r)[1] / 1e3 for r in ids])
+    st = srv.stats()
+    srv.close()
+    return lat, wall, st
+
+
+def serve_mix(F, N, dev, budget, nreq=1500, warm=200, load=0.8, seed=0):
+    """Served Poisson stream on the resident factorization (continuous
+    batching through mbf_server, 4 slots): 1..32 RHS per request, offered at
+    `load` times the capacity measured on a saturated mixed stream of the
+    same request sizes; p50 / p99 over the requests after a warm-up."""
     import numpy as np
     import torch
 
     import mbf_workloads as W
-    import paper_1509_07925_amd as mbf
 
     rng = np.random.default_rng(seed)
-    sizes = rng.integers(1, 33, size=nreq)
+    sizes = rng.integers(1, 33, size=nreq + warm)
     pool = torch.randn((64, N), dtype=torch.complex64, device=dev)  # request inputs drawn from here
     outs = [torch.empty((int(k), N), dtype=torch.complex64, device=dev).t() for k in sizes]
     ins = [pool[: int(k)].t() for k in sizes]
-    # offered load from a solo 32-RHS apply
-    t0 = time.perf_counter()
-    for _ in range(3):
-        F.apply(ins[0] if sizes[0] == 32 else pool[:32].t())
     torch.cuda.synchronize()
-    per_rhs = (time.perf_counter() - t0) / (3 * 32)
-    rate = 0.8 / (per_rhs * float(np.mean(sizes)))
-    arrivals = W.poisson_arrivals(nreq, rate, seed=seed)
-    srv = mbf.Server(mem_budget=24 << 30, nslots=4, max_batch_rhs=256)
-    t_start = time.perf_counter()
-    for i in range(nreq):
-        while time.perf_counter() - t_start < arrivals[i]:
-            pass
-        srv.submit(F, ins[i], outs[i])
-    srv.drain()
-    st = srv.stats()
-    srv.close()
-    return {"requests": int(st["requests"]), "rhs": int(st["rhs"]), "batches": int(st["batches"]),
-            "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
-            "rhs_per_s": round(st["rhs"] / st["wall_s"], 1) if st["wall_s"] > 0 else None,
-            "offered_rhs_per_s": round(rate * float(np.mean(sizes)), 1),
-            "max_concurrent_batches": int(st["max_concurrent_batches"])}
+    srv_args = dict(mem_budget=24 << 30, nslots=4, max_batch_rhs=256)
+    # capacity: every calibration request queued at once
+    ncal = min(300, nreq)
+    _, wall, st = _serve_run(srv_args, F, N, dev, ins[:ncal], outs[:ncal], np.zeros(ncal))
+    capacity = float(np.sum(sizes[:ncal])) / wall
+    rate = load * capacity / float(np.mean(sizes))
+    arrivals = W.poisson_arrivals(nreq + warm, rate, seed=seed)
+    if arrivals[-1] > budget.left() - 20:
+        keep = int(np.searchsorted(arrivals, max(budget.left() - 20, 1.0)))
+        arrivals, ins, outs, sizes = arrivals[:keep], ins[:keep], outs[:keep], sizes[:keep]
+        warm = min(warm, keep // 4)
+    lat, wall, st = _serve_run(srv_args, F, N, dev, ins, outs, arrivals)
+    lat = lat[warm:]
+    return {"requests": int(lat.size), "warmup_requests": int(warm), "load": load,
+            "capacity_rhs_per_s": round(capacity, 1), "offered_rhs_per_s": round(load * capacity, 1),
+            "served_rhs_per_s": round(float(np.sum(sizes)) / wall, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "batches": int(st["batches"]), "max_concurrent_batches": int(st["max_concurrent_batches"])}
 
 
-# Extra resident factorizations for the multi-factor serving leg: DFT and FIO
-# (polar and multiscale) at uneven sizes, beside the benchmark's own factor.
-SERVE_EXTRA = [
-    ("dft64", dict(kernel="dft", n=64, tol=1e-6, leaf=4, split="none")),
-    ("dft128", dict(kernel="dft", n=128, tol=1e-6, leaf=4, split="none")),
-    ("fio64polar", dict(kernel="fio", n=64, tol=1e-6, leaf=4, split="polar")),
-    ("fio128polar", dict(kernel="fio", n=128, tol=1e-6, leaf=4, split="polar")),
-    ("fio64ms", dict(kernel="fio", n=64, tol=1e-4, leaf=4, split="multiscale")),
-    ("fio128ms", dict(kernel="fio", n=128, tol=1e-4, leaf=4, split="multiscale")),
-]
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def serve_multi(main_name, F_main, N_main, dev, nreq=700, seed=1):
-    """Poisson stream over several resident factorizations of uneven N: each
-    request picks a factorization uniformly and has 1..32 RHS; continuous
-    batching per factorization through one mbf_server (4 slots), offered at
-    ~80% of the throughput estimated from solo 32-RHS applies."""
+def _host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(cfg, x, xi, g, u_gpu, out, reps=5):
+    """Oracle leg: the direct FP64 sum of eq. (kernel) on sampled rows (the
+    paper's error estimator and speed-up denominator), with all host cores
+    and with one, median of `reps` runs each, scaled to RHS/s over all rows;
+    for the DFT also the oracle's FFT closed form (numpy, one core) and the
+    same transform with scipy.fft on all cores."""
     import numpy as np
-    import torch
-
-    import mbf_workloads as W
-    import paper_1509_07925_amd as mbf
-
-    t0 = time.time()
-    facs = [(main_name, F_main, N_main)]
-    for name, c in SERVE_EXTRA:
-        if name == main_name:
-            continue
-        n = c["n"]
-        x, xi = (W.grid_x_integer(n), W.grid_omega(n)) if c["kernel"] == "dft" else (W.grid_x_unit(n), W.grid_omega(n))
-        facs.append((name, mbf.Factor.build(x, xi, n, kernel=c["kernel"], tol=c["tol"], leaf_side=c["leaf"],
-                                            split=c["split"], precs=["c64"], max_rank=4096), n * n))
-    log("multi-factor serving: %d factorizations resident (extra builds %.1fs)" % (len(facs), time.time() - t0))
-    rng = np.random.default_rng(seed)
-    which = rng.integers(0, len(facs), size=nreq)
-    sizes = rng.integers(1, 33, size=nreq)
-    pools = [torch.randn((32, N), dtype=torch.complex64, device=dev) for _, _, N in facs]
-    per_rhs = []
-    for (name, F, N), pool in zip(facs, pools):
-        F.apply(pool.t())
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(3):
-            F.apply(pool.t())
-        torch.cuda.synchronize()
-        per_rhs.append((time.perf_counter() - t1) / (3 * 32))
-    mean_service = float(np.mean([per_rhs[w] * k for w, k in zip(which, sizes)]))
-    rate = 0.8 / mean_service
-    arrivals = W.poisson_arrivals(nreq, rate, seed=seed)
-    ins = [pools[w][: int(k)].t() for w, k in zip(which, sizes)]
-    outs = [torch.empty((int(k), facs[w][2]), dtype=torch.complex64, device=dev).t() for w, k in zip(which, sizes)]
-    srv = mbf.Server(mem_budget=24 << 30, nslots=4, max_batch_rhs=256)
-    ids = []
-    t_start = time.perf_counter()
-    for i in range(nreq):
-        while time.perf_counter() - t_start < arrivals[i]:
-            pass
-        ids.append(srv.submit(facs[which[i]][1], ins[i], outs[i]))
-    srv.drain()
-    lat_ms = np.array([srv.poll(r)[1] / 1e3 for r in ids])
-    st = srv.stats()
-    srv.close()
-    per = {}
-    for j, (name, _, N) in enumerate(facs):
-        sel = lat_ms[which == j]
-        if sel.size:
-            per[name] = {"N": int(N), "requests": int(sel.size), "p50_ms": round(float(np.percentile(sel, 50)), 3),
-                         "p99_ms": round(float(np.percentile(sel, 99)), 3)}
-    return {"factorizations": len(facs), "requests": int(st["requests"]), "rhs": int(st["rhs"]),
-            "batches": int(st["batches"]), "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
-            "rhs_per_s": round(st["rhs"] / st["wall_s"], 1) if st["wall_s"] > 0 else None,
-            "offered_rhs_per_s": round(rate * float(np.mean(sizes)), 1),
-            "max_concurrent_batches": int(st["max_concurrent_batches"]), "per_factorization": per}
-
-
-def cpu_baseline(cfg, x, xi, g, u_gpu, out):
-    """Oracle leg: direct FP64 summation (eq. (kernel)) on sampled rows."""
     import threadpoolctl
 
     import mbf_workloads as W
@@ -439,19 +458,47 @@ def cpu_baseline(cfg, x, xi, g, u_gpu, out):
 
     n, nrhs = cfg["n"], g.shape[1]
     N = n * n
+    cores = _host_cores()
     K = kernels.dft(n) if cfg["kernel"] == "dft" else kernels.fio_radon(n)
-    # bounded sample: about 10 s of host work at n = 512
-    nrows = max(64, min(N, int(4096 * (256.0 / n) ** 2)))
-    rows = W.sample_rows(N, nrows, seed=1)
-    info = threadpoolctl.threadpool_info()
-    cores = max([i.get("num_threads", 1) for i in info] + [1])
-    t0 = time.perf_counter()
-    ref = direct.direct_rows(K, x, xi, g, rows, block=256)
-    dt = time.perf_counter() - t0
-    out["rel_err_vs_direct_sampled_rows"] = direct.rel_err(u_gpu[rows], ref)
-    return {"value": round(nrhs / (dt * N / nrows), 6), "unit": "RHS/s", "cores": int(cores), "kind": "oracle",
-            "sample": "direct FP64 sum of eq. (kernel) on %d of %d rows x %d RHS in %.2f s, "
-                      "scaled to the full N" % (nrows, N, nrhs, dt)}
+    rows = W.sample_rows(N, 256, seed=1)
+    out["rel_err_vs_direct_sampled_rows"] = direct.rel_err(u_gpu[rows], direct.direct_rows(K, x, xi, g, rows, block=256))
+
+    def med(fn):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    # bounded sample: about 2 s per run at n = 512 on 16 cores
+    nrows = max(16, min(N, int(256 * (512.0 / n) ** 2)))
+    rows_all = W.sample_rows(N, nrows, seed=2)
+    with threadpoolctl.threadpool_limits(cores):
+        t_all = med(lambda: direct.direct_rows(K, x, xi, g, rows_all, block=256))
+    rows_one = rows_all[: max(4, nrows // 16)]
+    with threadpoolctl.threadpool_limits(1):
+        t_one = med(lambda: direct.direct_rows(K, x, xi, g, rows_one, block=256))
+    res = {"value": round(nrhs / (t_all * N / nrows), 6), "unit": "RHS/s", "cores": int(cores), "kind": "oracle",
+           "sample": "direct FP64 sum of eq. (kernel) on %d of %d rows x %d RHS, median of %d runs %.2f s on %d "
+                     "threads, scaled to all rows" % (nrows, N, nrhs, reps, t_all, cores),
+           "cpu_model": _cpu_model(),
+           "direct_one_core": {"value": round(nrhs / (t_one * N / rows_one.size), 6), "unit": "RHS/s", "cores": 1,
+                               "sample": "%d rows, median of %d runs %.2f s" % (rows_one.size, reps, t_one)}}
+    if cfg["kernel"] == "dft" and cfg["split"] == "none":
+        import scipy.fft
+        nf = min(nrhs, 64)
+        gs = g[:, :nf]
+        with threadpoolctl.threadpool_limits(1):
+            t_fft1 = med(lambda: direct.dft_fft(n, gs))
+        G = np.ascontiguousarray(gs.T.reshape(nf, n, n))
+        t_fftc = med(lambda: scipy.fft.fft2(scipy.fft.ifftshift(G, axes=(1, 2)), axes=(1, 2), workers=cores))
+        res["fft_one_core"] = {"value": round(nf / t_fft1, 2), "unit": "RHS/s", "cores": 1,
+                               "sample": "oracle closed form (numpy fft2) on %d RHS, median of %d runs" % (nf, reps)}
+        res["fft_all_cores"] = {"value": round(nf / t_fftc, 2), "unit": "RHS/s", "cores": int(cores),
+                                "sample": "scipy.fft.fft2 with workers=%d on %d RHS, median of %d runs" % (
+                                    cores, nf, reps)}
+    return res
 
 
 if __name__ == "__main__":
