@@ -235,6 +235,22 @@ mbf_status mbf_workspace_size(mbf_factor f, mbf_prec p, int64_t nrhs, size_t* by
 mbf_status mbf_apply(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg, void* u,
                      int64_t ldu, void* workspace, size_t ws_bytes, void* stream);
 
+/* u = K g without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels as mbf_apply, with the workspace taken
+ * from a fixed device array of the library (mbf_scratch_bytes() bytes,
+ * 128 MiB; one copy per device, held until the process ends) instead of the
+ * caller's workspace.  Arguments as for mbf_apply.  Errors as mbf_apply,
+ * plus MBF_ERR_INVALID_ARG when the apply needs more workspace than the
+ * scratch holds (mbf_workspace_size(f, p, nrhs) > mbf_scratch_bytes(); use
+ * mbf_apply then).  The first call on a device looks up the scratch's
+ * address there.  All calls on one device share its scratch: calls that
+ * overlap on one device (concurrent streams or threads) race and must be
+ * serialized by the caller. */
+mbf_status mbf_apply_scratch(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg, void* u,
+                             int64_t ldu, void* stream);
+size_t mbf_scratch_bytes(void);
+
 /* v = K^* h: the chain of eq. (gbf) in reverse order with every factor
  * conjugate-transposed.  h: nx x nrhs (ld ldh), v: nxi x nrhs (ld ldv). */
 mbf_status mbf_apply_adjoint(mbf_factor f, mbf_prec p, int64_t nrhs, const void* h, int64_t ldh,

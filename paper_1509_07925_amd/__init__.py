@@ -77,7 +77,7 @@ EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
            "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
            "mbf_server_submit", "mbf_server_poll", "mbf_server_drain", "mbf_server_stats",
-           "mbf_server_destroy", "mbf_save", "mbf_load", "mbf_autotune"]
+           "mbf_server_destroy", "mbf_save", "mbf_load", "mbf_autotune", "mbf_apply_scratch", "mbf_scratch_bytes"]
 
 
 def lib():
@@ -97,6 +97,9 @@ def lib():
     L.mbf_workspace_size.argtypes = [vp, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
     L.mbf_apply.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
     L.mbf_apply_adjoint.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+    L.mbf_apply_scratch.argtypes = [vp, i32, i64, vp, i64, vp, i64, vp]
+    L.mbf_scratch_bytes.argtypes = []
+    L.mbf_scratch_bytes.restype = ctypes.c_size_t
     L.mbf_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.mbf_profile_begin.argtypes = [vp, i32]
     L.mbf_profile_end.argtypes = [vp, ctypes.POINTER(LaunchRecord), i32, ctypes.POINTER(i32)]
@@ -114,7 +117,7 @@ def lib():
     L.mbf_destroy.restype = None
     L.mbf_last_error.restype = ctypes.c_char_p
     for name in ("mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
-                 "mbf_apply_adjoint", "mbf_info", "mbf_profile_begin", "mbf_profile_end",
+                 "mbf_apply_adjoint", "mbf_apply_scratch", "mbf_info", "mbf_profile_begin", "mbf_profile_end",
                  "mbf_server_create", "mbf_server_submit", "mbf_server_poll", "mbf_server_drain",
                  "mbf_server_stats", "mbf_save", "mbf_load", "mbf_autotune"):
         getattr(L, name).restype = ctypes.c_int

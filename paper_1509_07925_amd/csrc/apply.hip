@@ -11,6 +11,7 @@
 //   dense_center      u += K_C g[Omega_C]       (multiscale, eq. (f1))
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "device.h"
@@ -816,6 +817,55 @@ size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs) {
     b = std::max(b, nchunk * (size_t)F.n_center * (size_t)nrhs * es);
   }
   return (b + 255) / 256 * 256;
+}
+
+// ------------------------------------------------------------------ scratch
+// Fixed device scratch of mbf_apply_scratch: the apply's workspace (the two
+// stage-state buffers, and the dense center's partial sums of a multiscale
+// adjoint) taken from a file-scope device array instead of caller memory.
+// Each device that runs the library holds its own copy until the process
+// ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.  No part of it needs
+// to start at zero: every stage writes its whole output state before the
+// next one reads it.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+Error scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return {MBF_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e)};
+  if (dev < 0 || dev >= kMaxDevices) return {MBF_ERR_UNSUPPORTED, "device index beyond the scratch table"};
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return {MBF_ERR_HIP, std::string("hipGetSymbolAddress (scratch): ") + hipGetErrorString(e)};
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return {MBF_OK, ""};
+}
+}  // namespace
+
+size_t scratch_bytes() { return kScratchBytes; }
+
+Error launch_apply_scratch(const DevFactor& F, int prec, int64_t nrhs, const void* in, int64_t ldin, void* out,
+                           int64_t ldout, hipStream_t st) {
+  const size_t need = workspace_bytes(F, prec, nrhs);
+  if (need > kScratchBytes)
+    return {MBF_ERR_INVALID_ARG, "apply needs " + std::to_string(need) + " bytes of workspace, above the " +
+                                     std::to_string(kScratchBytes) + "-byte device scratch: use mbf_apply"};
+  void* ws = nullptr;
+  Error e = scratch_address(&ws);
+  if (e.st != MBF_OK) return e;
+  return launch_apply(F, prec, false, nrhs, in, ldin, out, ldout, ws, kScratchBytes, st);
 }
 
 Error launch_apply(const DevFactor& F, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,

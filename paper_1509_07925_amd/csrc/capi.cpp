@@ -293,6 +293,19 @@ mbf_status mbf_apply(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int6
   return apply_common(f, p, false, nrhs, g, ldg, u, ldu, workspace, ws_bytes, stream);
 }
 
+mbf_status mbf_apply_scratch(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg, void* u,
+                             int64_t ldu, void* stream) {
+  if (!f || !valid_prec(p) || nrhs < 0) return fail(MBF_ERR_INVALID_ARG, "invalid argument");
+  if (!(f->dev.prec_mask & (1u << p))) return fail(MBF_ERR_UNSUPPORTED, "precision not built for this factor");
+  if (nrhs == 0) return MBF_OK;
+  if (nrhs > 65535 * 32) return fail(MBF_ERR_INVALID_ARG, "too many right-hand sides");
+  if (!g || !u) return fail(MBF_ERR_INVALID_ARG, "null device pointer");
+  if (ldg < f->dev.nxi || ldu < f->dev.nx) return fail(MBF_ERR_INVALID_ARG, "leading dimension too small");
+  return from(launch_apply_scratch(f->dev, p, nrhs, g, ldg, u, ldu, (hipStream_t)stream));
+}
+
+size_t mbf_scratch_bytes(void) { return scratch_bytes(); }
+
 mbf_status mbf_apply_adjoint(mbf_factor f, mbf_prec p, int64_t nrhs, const void* h, int64_t ldh, void* v,
                              int64_t ldv, void* workspace, size_t ws_bytes, void* stream) {
   return apply_common(f, p, true, nrhs, h, ldh, v, ldv, workspace, ws_bytes, stream);

@@ -118,6 +118,11 @@ Error autotune_factor(const DevFactor& F, int prec, int64_t nrhs, void* ws, size
 Error launch_apply(const DevFactor& F, int prec, bool adjoint, int64_t nrhs, const void* in,
                    int64_t ldin, void* out, int64_t ldout, void* ws, size_t ws_bytes,
                    hipStream_t stream);
+// u = K g with the workspace in the library's fixed device scratch (no
+// allocation); fails when the apply needs more than scratch_bytes().
+Error launch_apply_scratch(const DevFactor& F, int prec, int64_t nrhs, const void* in, int64_t ldin, void* out,
+                           int64_t ldout, hipStream_t stream);
+size_t scratch_bytes();
 
 }  // namespace mbf
 
