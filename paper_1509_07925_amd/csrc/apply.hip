@@ -11,6 +11,7 @@
 //   dense_center      u += K_C g[Omega_C]       (multiscale, eq. (f1))
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <mutex>
 #include <string>
 
@@ -631,6 +632,13 @@ inline int64_t stage_nnz(const DevPart& P, int s) {
   return e - P.w_stage_off[s];
 }
 
+// MBF_BF16_SPLIT_STATE=0 keeps FP32 states between the split-BF16 stages
+// (every stage then splits its input as it stages it through LDS).
+bool split_state_enabled() {
+  const char* e = std::getenv("MBF_BF16_SPLIT_STATE");
+  return !(e && e[0] == '0');
+}
+
 template <typename T>
 Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int64_t nrhs, const void* in,
                int64_t ldin, void* out, int64_t ldout, void* ws, int64_t ws_ld, bool accumulate,
@@ -665,6 +673,17 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       hipLaunchKernelGGL(k_leaf_project<T>, dim3(nleaf, nt), dim3(256), 0, st, lv, Fl, idx,
                          reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
   };
+  // Split BF16: the stage kernels pass the state between stages as BF16
+  // hi | lo words; the first stage splits the projected FP32 state, the last
+  // one writes FP32 for the leaf reconstruction.
+  const bool split = prec == MBF_C64_SPLIT_BF16 && ws_ld < ((int64_t)1 << 23) && split_state_enabled() &&
+                     split_choice(prec, ws_ld, ni) != 0;
+  int s_lo = L, s_hi = -1;  // first and last stage with blocks
+  for (int s = 0; s < L; ++s)
+    if (P.nblk[s] > 0) {
+      s_lo = std::min(s_lo, s);
+      s_hi = s;
+    }
   auto reconstruct = [&](bool small, int32_t nleaf, int32_t max_np, const LeafDesc* lv, const C* Fl,
                          const int32_t* idx, const C* src, int64_t ldsrc, int acc) {
     if (small)
@@ -688,7 +707,8 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       Timed t(pr, st, 1, pidx, s, prec, fl, by);
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
         Error e = launch_stage_mfma(P, s, prec, false, bd, pd.Wst[s], buf[s & 1], P.ld[s], buf[(s + 1) & 1],
-                                    P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st);
+                                    P.ld[s + 1], ni, reinterpret_cast<const float*>(sc), st, split && s != s_lo,
+                                    split && s != s_hi);
         if (e.st != MBF_OK) return e;
       } else if (prec == MBF_C64) {
         Error e = launch_stage_r16(P, s, false, bd, pd.Wst[s], buf[s & 1], P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni,
@@ -719,7 +739,8 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       Timed t(pr, st, 1, pidx, s, prec, fl, by);
       if (prec != MBF_C128 && use_mfma(P, s, nrhs, prec)) {
         Error e = launch_stage_mfma(P, s, prec, true, bd, pd.Wst[s], buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1],
-                                    P.ld[s], ni, reinterpret_cast<const float*>(sc), st);
+                                    P.ld[s], ni, reinterpret_cast<const float*>(sc), st, split && s != s_hi,
+                                    split && s != s_lo);
         if (e.st != MBF_OK) return e;
       } else if (prec == MBF_C64) {
         Error e = launch_stage_r16(P, s, true, bd, pd.Wst[s], buf[(s + 1) & 1], P.ld[s + 1], buf[s & 1], P.ld[s], ni,
@@ -795,15 +816,58 @@ Error autotune_factor(const DevFactor& F, int prec, int64_t nrhs, void* ws, size
     for (int s = 0; s < P.L; ++s) {
       if (P.nblk[s] == 0 || !use_mfma(P, s, nrhs, prec)) continue;
       const BlockDesc* bd = P.d_blk + P.blk_first[s];
-      for (int adj = 0; adj < 2; ++adj) {
-        Error e = adj ? autotune_stage(P, s, prec, true, bd, P.prec[prec].Wst[s], buf[(s + 1) & 1], P.ld[s + 1],
-                                       buf[s & 1], P.ld[s], (int)nrhs, st, nullptr, nullptr)
-                      : autotune_stage(P, s, prec, false, bd, P.prec[prec].Wst[s], buf[s & 1], P.ld[s],
-                                       buf[(s + 1) & 1], P.ld[s + 1], (int)nrhs, st, nullptr, nullptr);
-        if (e.st != MBF_OK) return e;
-        if (ntuned) ++*ntuned;
-      }
+      // split BF16: the kernels of FP32 inputs (first stage) and of split inputs
+      for (int fam = 0; fam < (prec == MBF_C64_SPLIT_BF16 ? 2 : 1); ++fam)
+        for (int adj = 0; adj < 2; ++adj) {
+          Error e = adj ? autotune_stage(P, s, prec, fam == 1, true, bd, P.prec[prec].Wst[s], buf[(s + 1) & 1],
+                                         P.ld[s + 1], buf[s & 1], P.ld[s], (int)nrhs, st, nullptr, nullptr)
+                        : autotune_stage(P, s, prec, fam == 1, false, bd, P.prec[prec].Wst[s], buf[s & 1],
+                                         P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], (int)nrhs, st, nullptr, nullptr);
+          if (e.st != MBF_OK) return e;
+          if (ntuned) ++*ntuned;
+        }
     }
+  }
+  if (prec == MBF_C64_SPLIT_BF16 && ws_ld < ((int64_t)1 << 23)) {
+    // split or FP32 states between the stages: time both forward stage chains
+    char* b0 = reinterpret_cast<char*>(ws);
+    char* buf[2] = {b0, b0 + (size_t)ws_ld * nrhs * 8};
+    auto chain = [&](bool on) -> Error {
+      for (const auto& P : F.parts) {
+        int s_lo = P.L, s_hi = -1;
+        for (int s = 0; s < P.L; ++s)
+          if (P.nblk[s] > 0) s_lo = std::min(s_lo, s), s_hi = s;
+        for (int s = 0; s < P.L; ++s) {
+          if (P.nblk[s] == 0) continue;
+          Error e = launch_stage_mfma(P, s, prec, false, P.d_blk + P.blk_first[s], P.prec[prec].Wst[s], buf[s & 1],
+                                      P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], (int)nrhs, nullptr, st,
+                                      on && s != s_lo, on && s != s_hi);
+          if (e.st != MBF_OK) return e;
+        }
+      }
+      return {MBF_OK, ""};
+    };
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return {MBF_ERR_HIP, "hipEventCreate"};
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return {MBF_ERR_HIP, "hipEventCreate"};
+    }
+    float ms[2] = {0.f, 0.f};
+    Error err{MBF_OK, ""};
+    for (int on = 0; on < 2 && err.st == MBF_OK; ++on) {
+      err = chain(on == 1);  // warm-up
+      if (err.st != MBF_OK) break;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 2 && err.st == MBF_OK; ++r) err = chain(on == 1);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) err = {MBF_ERR_HIP, "autotune timing"};
+      else (void)hipEventElapsedTime(&ms[on], e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err.st != MBF_OK) return err;
+    set_split_choice(prec, ws_ld, (int)nrhs, ms[1] <= ms[0]);
   }
   return {MBF_OK, ""};
 }

@@ -151,6 +151,51 @@ __device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int
   }
 }
 
+// Split state of the BF16 x3 kernels: each complex entry x becomes the two
+// words hi = Re_hi | Im_hi << 16 and lo = Re_lo | Im_lo << 16 (BF16 bits),
+// stored where the FP32 (Re, Im) pair would be: the 8 bytes of entry (n, row)
+// are (hi, lo).  kInSplit / kOutSplit: the input / output state of a launch
+// is split.
+constexpr int kInSplit = 1, kOutSplit = 2;
+
+// store_out writing the split state.  Lane pairs (2i, 2i+1) hold the real
+// and imaginary part of one complex entry; each lane splits its value, the
+// pair swaps one half (DPP quad permutation 1,0,3,2), and the even lane
+// stores the hi word, the odd lane the lo word: the addresses, hence the
+// coalescing, of the FP32 store.
+template <bool ADJ, int RT, int CT>
+__device__ __forceinline__ void store_out_split(const BlockDesc& d, int R, int r0, int n0,
+                                                const v16f (&acc)[RT][CT], int wn, int wm, float2* __restrict__ out,
+                                                int64_t ld_out, int nrhs, const float* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const bool odd = lane & 1;
+  uint32_t* o = reinterpret_cast<uint32_t*>(out);
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = wm + c * 32 + (lane & 31);
+    const int m = r0 + (col >> 1);
+    const bool mok = m < R;  // uniform over each lane pair
+    const int32_t row = ADJ ? d.in_row + min(m, R - 1) : grp_row(d, min(m, R - 1));
+    const float sc = scale ? scale[row] : 1.0f;
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int n = n0 + wn + 32 * a + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        uint32_t hi, lo;
+        // The product is rounded first, as the FP32 store rounds it: the empty
+        // asm keeps the compiler from fusing it into the lo residual (the
+        // split is then that of the FP32 value, bit for bit).
+        float x = acc[a][c][j] * sc;
+        asm volatile("" : "+v"(x));
+        split_bf(x, hi, lo);
+        const uint32_t recv = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(odd ? hi : lo), 0xB1, 0xF, 0xF, false);
+        const uint32_t w = odd ? (recv | (lo << 16)) : (hi | (recv << 16));
+        if (mok && n < nrhs) o[2 * ((int64_t)n * ld_out + row) + (col & 1)] = w;
+      }
+  }
+}
+
 // ------------------------------------------------------------------ loads
 // Each chunk moves a TNV x 16 tile of the input state (A) and a 16 x TMV
 // tile of the block (B) into registers, consecutive lanes on consecutive
@@ -160,7 +205,7 @@ __device__ __forceinline__ void store_out(const BlockDesc& d, int R, int r0, int
 //                 the 4 entries W(m, 4g .. 4g+3) (lanes along m)
 //   B adjoint:    pair p = tid + j NTH: group g = p % 4, row k' = p / 4;
 //                 the 4 entries W(4g .. 4g+3, k') (contiguous)
-template <class S, bool ADJ, typename WT>
+template <class S, bool ADJ, typename WT, bool LOAD_A = true>
 struct Loader {
   float2 a[S::EA];
   WT b[S::EB][4];
@@ -183,7 +228,7 @@ struct Loader {
     constexpr int NTH = S::NTH, TMV = S::TMV;
     const int tid = threadIdx.x;
     ok = 0;
-    {
+    if constexpr (LOAD_A) {
       const int k = tid % KCH, n = tid / KCH;
       const int q = q0 + k;
       const int qc = min(q, Q - 1);
@@ -219,9 +264,11 @@ struct Loader {
   }
   // Zero the entries outside the block.
   __device__ __forceinline__ void finish() {
+    if constexpr (LOAD_A) {
 #pragma unroll
-    for (int j = 0; j < S::EA; ++j)
-      if (!((ok >> j) & 1)) a[j] = make_float2(0.f, 0.f);
+      for (int j = 0; j < S::EA; ++j)
+        if (!((ok >> j) & 1)) a[j] = make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int j = 0; j < S::EB; ++j)
 #pragma unroll
@@ -251,7 +298,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32(const BlockDesc* __restric
                                                       const float2* __restrict__ in, int64_t ld_in,
                                                       float2* __restrict__ out, int64_t ld_out, int nrhs,
                                                       const float* __restrict__ scale, int mtiles, int ntiles,
-                                                      int64_t total) {
+                                                      int64_t total, int /*flags*/) {
   constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
   __shared__ __attribute__((aligned(16))) float As[NB][2][TNV * PA];        // [buf][re|im][n][k]
   // block operand: [buf][plane][bidx_pad], two planes of 2 TMV x PA words
@@ -413,7 +460,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32_3m(const BlockDesc* __rest
                                                          const float2* __restrict__ in, int64_t ld_in,
                                                          float2* __restrict__ out, int64_t ld_out, int nrhs,
                                                          const float* __restrict__ scale, int mtiles, int ntiles,
-                                                         int64_t total) {
+                                                         int64_t total, int /*flags*/) {
   constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
   __shared__ __attribute__((aligned(16))) float As[NB][3][TNV * PA];  // [buf][Xr|Xi|Xr+Xi][n][k]
   __shared__ __attribute__((aligned(16))) float Bs[NB][3][TMV * PA];  // [buf][Br|Bi|Br+Bi][m][k]
@@ -551,6 +598,38 @@ __global__ __launch_bounds__(S::NTH) void k_stage_f32_3m(const BlockDesc* __rest
 }
 
 // ------------------------------------------------------------------ BF16 x3
+// Block operand of a chunk (registers -> LDS): the BF16 pairs of the real
+// embedding, hi and lo parts in separate arrays (bidx layout).
+template <bool ADJ, class S, class LD>
+__device__ __forceinline__ void stash_block_bf16(const LD& c, uint32_t* __restrict__ Bh, uint32_t* __restrict__ Bl) {
+#pragma unroll
+  for (int j = 0; j < S::EB; ++j) {
+    int mrow, g;
+    LD::pair_pos(j, mrow, g);
+    uint32_t h0[4], h1[4], l0[4], l1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint2 w = c.b[j][i];
+      const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
+      if (!ADJ) {  // column 2m: (Wr, -Wi);  column 2m+1: (Wi, Wr)
+        h0[i] = reh | ((imh ^ 0x8000u) << 16);
+        h1[i] = imh | (reh << 16);
+        l0[i] = rel | ((iml ^ 0x8000u) << 16);
+        l1[i] = iml | (rel << 16);
+      } else {  // conj(W): column 2k': (Wr, Wi);  column 2k'+1: (-Wi, Wr)
+        h0[i] = reh | (imh << 16);
+        h1[i] = (imh ^ 0x8000u) | (reh << 16);
+        l0[i] = rel | (iml << 16);
+        l1[i] = (iml ^ 0x8000u) | (rel << 16);
+      }
+    }
+    *reinterpret_cast<uint4*>(&Bh[bidx(mrow, 0, g)]) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
+    *reinterpret_cast<uint4*>(&Bh[bidx(mrow, 1, g)]) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
+    *reinterpret_cast<uint4*>(&Bl[bidx(mrow, 0, g)]) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
+    *reinterpret_cast<uint4*>(&Bl[bidx(mrow, 1, g)]) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
+  }
+}
+
 // LDS words hold two BF16 values along the reduction: the state word (n, k)
 // is (Re, Im) of x(n, k); the block words are the matching pairs of the
 // embedding.  The split products carry ~2^-16 relative error, so the partial
@@ -561,7 +640,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
                                                          const float2* __restrict__ in, int64_t ld_in,
                                                          float2* __restrict__ out, int64_t ld_out, int nrhs,
                                                          const float* __restrict__ scale, int mtiles, int ntiles,
-                                                         int64_t total) {
+                                                         int64_t total, int flags) {
   constexpr int NTH = S::NTH, TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT, NB = S::NB;
   __shared__ __attribute__((aligned(16))) uint32_t Ah[NB][TNV * PA], Al[NB][TNV * PA];
   __shared__ __attribute__((aligned(16))) uint32_t Bh[NB][TMV * 2 * KCH], Bl[NB][TMV * 2 * KCH];
@@ -590,32 +669,7 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
       Ah[buf][(n + j * (NTH / KCH)) * PA + k] = rh | (ih << 16);
       Al[buf][(n + j * (NTH / KCH)) * PA + k] = rl | (il << 16);
     }
-#pragma unroll
-    for (int j = 0; j < S::EB; ++j) {
-      int mrow, g;
-      LD::pair_pos(j, mrow, g);
-      uint32_t h0[4], h1[4], l0[4], l1[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint2 w = c.b[j][i];
-        const uint32_t reh = w.x & 0xffffu, imh = w.x >> 16, rel = w.y & 0xffffu, iml = w.y >> 16;
-        if (!ADJ) {  // column 2m: (Wr, -Wi);  column 2m+1: (Wi, Wr)
-          h0[i] = reh | ((imh ^ 0x8000u) << 16);
-          h1[i] = imh | (reh << 16);
-          l0[i] = rel | ((iml ^ 0x8000u) << 16);
-          l1[i] = iml | (rel << 16);
-        } else {  // conj(W): column 2k': (Wr, Wi);  column 2k'+1: (-Wi, Wr)
-          h0[i] = reh | (imh << 16);
-          h1[i] = (imh ^ 0x8000u) | (reh << 16);
-          l0[i] = rel | (iml << 16);
-          l1[i] = (iml ^ 0x8000u) | (rel << 16);
-        }
-      }
-      *reinterpret_cast<uint4*>(&Bh[buf][bidx(mrow, 0, g)]) = make_uint4(h0[0], h0[1], h0[2], h0[3]);
-      *reinterpret_cast<uint4*>(&Bh[buf][bidx(mrow, 1, g)]) = make_uint4(h1[0], h1[1], h1[2], h1[3]);
-      *reinterpret_cast<uint4*>(&Bl[buf][bidx(mrow, 0, g)]) = make_uint4(l0[0], l0[1], l0[2], l0[3]);
-      *reinterpret_cast<uint4*>(&Bl[buf][bidx(mrow, 1, g)]) = make_uint4(l1[0], l1[1], l1[2], l1[3]);
-    }
+    stash_block_bf16<ADJ, S>(c, Bh[buf], Bl[buf]);
   };
   v16f acc[RT][CT];
 #pragma unroll
@@ -683,7 +737,309 @@ __global__ __launch_bounds__(S::NTH) void k_stage_bf16x3(const BlockDesc* __rest
       }
     }
   }
-  store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+  if (flags & kOutSplit)
+    store_out_split<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+  else
+    store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+}
+
+// ------------------------------------------------------------------ BF16 x3, split input
+// Interior stages read a split state (kInSplit).  Both operands then move
+// from memory into LDS by buffer loads that write LDS directly: no registers
+// and no VALU work per chunk (per-lane offsets are fixed per tile, the chunk
+// advances through the scalar offset), three chunks deep (chunks q + 1 and
+// q + 2 load while q is summed).  The state operand is 2 right-hand sides x
+// 16 reduction entries x (hi, lo) per load (two 128-byte runs), in LDS
+// [n][8 groups of (hi, lo, hi, lo)] with the group of entries (2 g, 2 g + 1)
+// at position g ^ ((n / 2) % 8), so that the 16-byte reads of 16 consecutive
+// rows fall on distinct banks.  The block operand is read raw (see the block
+// loads below); the real embedding (per output-column parity, a swap of the
+// BF16 halves and a sign) is applied as
+// the operands are read.  Every load reads whole 128-byte lines: the memory
+// pipeline holds a bounded number of requests per CU, and loads that gather
+// short pieces from many lines run several times slower.
+// Reads past the block take clamped addresses, except the block operand's
+// reduction entries past the end, which read zero (offsets past the buffer
+// range); right-hand sides and output rows past the block are not stored.  Vector
+// memory operations complete in issue order, so waiting until at most one
+// chunk's loads are outstanding completes the chunk before it.  Loads are
+// also issued past the last chunk (clamped, into buffers not read again) so
+// that this count holds on every iteration.
+template <class S>
+struct DmaShape {
+  static constexpr int NW = S::NTH / 64;            // waves
+  static constexpr int NIA = S::TNV * 32 / S::NTH;  // state loads per wave per chunk
+  static constexpr int NIB = S::TMV * 32 / S::NTH;  // block loads per wave per chunk (both planes)
+  static constexpr int NI = NIA + NIB;
+  static_assert(NIA * NW == S::TNV / 2 && NIB * NW == S::TMV / 2, "LDS load mapping");
+  static_assert(NIA % 8 == 0 && NI <= 63 && S::TMV % 32 == 0, "LDS load mapping");
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource (stride 0) over [base, base + bytes): loads at offsets
+// past the end return zero.
+// (base and bytes are uniform; read from the first lane so that the compiler
+// holds them in scalar registers, as the instruction requires)
+__device__ __forceinline__ v4i buffer_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t b = reinterpret_cast<uint64_t>(base);
+  return v4i{__builtin_amdgcn_readfirstlane((int)(uint32_t)b),
+             __builtin_amdgcn_readfirstlane((int)((uint32_t)(b >> 32) & 0xffffu)),
+             __builtin_amdgcn_readfirstlane((int)bytes), 0x00020000};
+}
+
+// One dword per lane from rs + voff + soff into LDS at lds + 4 lane (the
+// buffer load's LDS form).  Written as assembly so that the compiler, which
+// would otherwise make every later LDS read wait for all such loads, leaves
+// the waits to the kernel (explicit s_waitcnt before the barriers that
+// publish a buffer).  The instruction has no register result.
+__device__ __forceinline__ void lds_load_dword(v4i rs, const uint32_t* lds, uint32_t voff, uint32_t soff) {
+  const uint32_t a = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)lds);
+  asm volatile("" : "+s"(soff));  // a register even when the offset is a known constant
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, %3 offen lds" ::"s"(a), "v"(voff), "s"(rs), "s"(soff)
+               : "memory");
+}
+
+// s_waitcnt immediate: at most n vector-memory operations outstanding, no
+// LDS operation outstanding (no wait on export counts).
+constexpr int vm_lgkm0(int n) { return (n & 15) | (0x7 << 4) | ((n >> 4) << 14); }
+
+template <bool ADJ, class S>
+__global__ __launch_bounds__(S::NTH) void k_stage_bf16x3_dma(const BlockDesc* __restrict__ blk,
+                                                             const uint2* __restrict__ W,
+                                                             const float2* __restrict__ in, int64_t ld_in,
+                                                             float2* __restrict__ out, int64_t ld_out, int nrhs,
+                                                             const float* __restrict__ scale, int mtiles,
+                                                             int ntiles, int64_t total, int flags) {
+  constexpr int TMV = S::TMV, TNV = S::TNV, RT = S::RT, CT = S::CT;
+  using DS = DmaShape<S>;
+  // One array per buffer, each accessed through a constant address: the
+  // compiler then knows which buffer a pending LDS load writes and does not
+  // make reads of the other buffers wait for it.
+  __shared__ __attribute__((aligned(16))) uint32_t As0[2][TNV * KCH], As1[2][TNV * KCH], As2[2][TNV * KCH];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs0[2][TMV * KCH], Bs1[2][TMV * KCH], Bs2[2][TMV * KCH];
+  static_assert(2 * TMV * KCH == 64 * DmaShape<S>::NIB * (S::NTH / 64), "block loads fill the buffer");
+  const Tile tl = map_tile(total, mtiles, ntiles);
+  if (tl.b < 0) return;
+  const BlockDesc d = blk[tl.b];
+  const int R = ADJ ? d.K : d.M;
+  const int Q = ADJ ? d.M : d.K;
+  const int r0 = tl.mt * TMV;
+  if (r0 >= R) return;
+  const int n0 = tl.nt * TNV;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wn = (wave % S::WR) * 32 * RT, wm = (wave / S::WR) * 32 * CT;
+  // State loads: load t = wave NIA + i holds right-hand sides 2 t + l / 32;
+  // lane l fills word p = l % 32 of its LDS row: group p / 4 holds entries
+  // (2 g, 2 g + 1) with g = (p / 4) ^ (t % 8) (t % 8 = i % 8: NIA is a
+  // multiple of 8), word p % 4 is (hi, lo, hi, lo)[...] of them.
+  const int nl = lane >> 5, p32 = lane & 31;
+  // reduction entry of lane l in loads with i % 8 = j
+  auto ka = [&](int j) __attribute__((always_inline)) { return 2 * ((p32 >> 2) ^ j) + ((p32 >> 1) & 1); };
+  const uint32_t pla = 4u * (lane & 1);  // hi / lo word
+  // one buffer resource per wave, based at its first right-hand side
+  // (offsets stay below 8 ld_in (2 NIA + 2) bytes: ld_in < 2^23)
+  const bool full = n0 + TNV <= nrhs;  // (uniform) no right-hand side of the tile is clamped
+  const int nb0 = min(n0 + 2 * wave * DS::NIA, nrhs - 1);
+  const v4i rsa = buffer_rsrc(in + (int64_t)nb0 * ld_in, 0xffffffffu);
+  const uint32_t stepa = 16u * (uint32_t)ld_in;  // bytes between consecutive loads' right-hand sides
+  uint32_t va[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) va[j] = 8u * (uint32_t)(nl * ld_in + ka(j)) + pla;
+  // block (W column-major M x K, 8 bytes per entry): output row (forward m,
+  // adjoint k') clamped into the block, reduction word through the scalar offset
+  const int M = d.M;
+  // (range: the block, so that the past-the-end offset below reads zero)
+  const v4i rsb = buffer_rsrc(W + d.w_off, 8u * (uint32_t)M * (uint32_t)d.K);
+  // Block loads: each reads contiguous runs of the column-major block (hi and
+  // lo words of consecutive entries, lanes alternating between them).
+  //   forward: load t = wave NIB + i holds reduction entry k = t / (TMV / 32)
+  //            and output rows m = 32 (t % (TMV / 32)) + l / 2 (256 bytes);
+  //            LDS [k][m][hi, lo] (words 2 TMV k + 2 m + plane).
+  //   adjoint: load t holds output columns k' = 2 t + l / 64 .. and reduction
+  //            entries m = 2 g + w / 2 (two runs of 128 bytes); LDS
+  //            [k'][8 groups of (hi, lo, hi, lo)], the group of m / 2 at
+  //            position (m / 2) ^ ((k' / 2) % 8) so that 16-byte reads of 16
+  //            consecutive columns fall on distinct banks.
+  // forward: the entry k of a load is uniform (scalar offset); the lane part
+  // repeats with period TMV / 32 in i (NIB is a multiple of it)
+  constexpr int NVB = ADJ ? DS::NIB : (DS::NIB < TMV / 32 ? DS::NIB : TMV / 32);
+  static_assert(ADJ || DS::NIB % NVB == 0, "block load pattern");
+  uint32_t vb[NVB];
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) {
+    const int t = wave * DS::NIB + i;
+    if (!ADJ) {
+      const int m = 32 * (t % (TMV / 32)) + (lane >> 1);
+      vb[i] = 8u * (uint32_t)min(r0 + m, R - 1) + 4u * (lane & 1);
+    } else {
+      const int r = 2 * t + (lane >> 5), p = lane & 31, g = (p >> 2) ^ (t & 7), w4 = p & 3;
+      vb[i] = 8u * (uint32_t)(min(r0 + r, R - 1) * M + 2 * g + (w4 >> 1)) + 4u * (w4 & 1);
+    }
+  }
+  auto kfw = [&](int i) __attribute__((always_inline)) { return (wave * DS::NIB + i) / (TMV / 32); };
+  // Loads of a chunk: NI per wave, load j < NIA of the state, the rest of the
+  // block.  The plan (uniform) holds what is common to a chunk's loads; the
+  // input rows of [q0, q0 + 16) are contiguous from rowbase + q0 when the
+  // chunk lies inside the block and inside one input group.
+  struct Plan {
+    int q0;
+    int32_t rowbase;
+    bool fasta, fast;
+  };
+  auto plan = [&](int q0) __attribute__((always_inline)) {
+    Plan p{q0, d.in_row, false, q0 + KCH <= Q};
+    p.fasta = full && p.fast;
+    if (ADJ) {  // the group holding q0 (selects, as in grp_row)
+      int32_t end = d.ms[1];
+      p.rowbase = d.orow[0] - d.ms[0];
+      if (q0 >= d.ms[1]) p.rowbase = d.orow[1] - d.ms[1], end = d.ms[2];
+      if (q0 >= d.ms[2]) p.rowbase = d.orow[2] - d.ms[2], end = d.ms[3];
+      if (q0 >= d.ms[3]) p.rowbase = d.orow[3] - d.ms[3], end = Q;
+      p.fasta = p.fasta && q0 + KCH <= end;
+    }
+    return p;
+  };
+  auto dma = [&](uint32_t (*As)[TNV * KCH], uint32_t (*Bs)[TMV * KCH], const Plan& p, int j)
+                 __attribute__((always_inline)) {
+    const int q0 = p.q0;
+    if (j < DS::NIA) {
+      const int i = j;
+      uint32_t* dst = &As[0][64 * (DS::NIA * wave + i)];
+      if (p.fasta) {  // (uniform)
+        lds_load_dword(rsa, dst, va[i & 7], 8u * (uint32_t)(p.rowbase + q0) + i * stepa);
+      } else {
+        const int q = min(q0 + ka(i & 7), Q - 1);
+        const int32_t row = ADJ ? grp_row(d, q) : d.in_row + q;
+        const int nr = min(n0 + 2 * (wave * DS::NIA + i) + nl, nrhs - 1) - nb0;
+        lds_load_dword(rsa, dst, 8u * (uint32_t)(nr * ld_in + row) + pla, 0u);
+      }
+    } else {
+      const int i = j - DS::NIA;
+      uint32_t* dst = &Bs[0][64 * (DS::NIB * wave + i)];
+      if (p.fast) {  // (uniform)
+        if (ADJ)
+          lds_load_dword(rsb, dst, vb[i % NVB], 8u * (uint32_t)q0);
+        else
+          lds_load_dword(rsb, dst, vb[i % NVB], 8u * (uint32_t)((q0 + kfw(i)) * M));
+      } else {  // reduction entries past the block read zero (offset past the range)
+        const int t = wave * DS::NIB + i;
+        int q;
+        if (!ADJ) {
+          q = q0 + t / (TMV / 32);
+        } else {
+          const int pp = lane & 31, g = (pp >> 2) ^ (t & 7);
+          q = q0 + 2 * g + ((pp & 3) >> 1);
+        }
+        const uint32_t off = ADJ ? vb[i % NVB] + 8u * (uint32_t)q0 : vb[i % NVB] + 8u * (uint32_t)(q * M);
+        lds_load_dword(rsb, dst, q < Q ? off : 0xfffffff0u, 0u);
+      }
+    }
+  };
+  auto issue = [&](uint32_t (*As)[TNV * KCH], uint32_t (*Bs)[TMV * KCH], int q0) __attribute__((always_inline)) {
+    const Plan p = plan(q0);
+#pragma unroll
+    for (int j = 0; j < DS::NI; ++j) dma(As, Bs, p, j);
+  };
+  v16f acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[a][c] = v16f{};
+  const int kh = lane >> 5, li = lane & 31;
+  // Embedding of a raw block word (Re | Im << 16) for this lane's real output
+  // column 2 m + (li & 1): forward (Wr, -Wi) | (Wi, Wr), adjoint (conj W)
+  // (Wr, Wi) | (-Wi, Wr); i.e. rotate by 16 bits for odd columns, then flip
+  // one sign bit.
+  const uint32_t rot = (li & 1) ? 16u : 0u;
+  const uint32_t sgn = ADJ ? ((li & 1) ? 0x8000u : 0u) : ((li & 1) ? 0u : 0x80000000u);
+  auto embed = [&](uint4 w) __attribute__((always_inline)) {
+    uint32_t e[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[j] = __builtin_amdgcn_alignbit(e[j], e[j], rot) ^ sgn;
+    return __builtin_bit_cast(bf16x8, make_uint4(e[0], e[1], e[2], e[3]));
+  };
+  auto compute = [&](const uint32_t (*As)[TNV * KCH], const uint32_t (*Bs)[TMV * KCH]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int kb = 0; kb < KCH; kb += 8) {
+      const int ko = kb + 4 * kh;
+      bf16x8 ah[RT], al[RT], bh[CT], bl[CT];
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const int n = wn + 32 * a + li, sw = (n >> 1) & 7;
+        const uint32_t* b = &As[0][0] + 32 * n;
+        const uint4 u = *reinterpret_cast<const uint4*>(b + 4 * ((ko >> 1) ^ sw));
+        const uint4 v = *reinterpret_cast<const uint4*>(b + 4 * (((ko >> 1) + 1) ^ sw));
+        ah[a] = __builtin_bit_cast(bf16x8, make_uint4(u.x, u.z, v.x, v.z));
+        al[a] = __builtin_bit_cast(bf16x8, make_uint4(u.y, u.w, v.y, v.w));
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int r = (wm + 32 * c + li) >> 1;  // output row (forward m, adjoint k') of the tile
+        uint2 x0, x1, x2, x3;                   // (hi, lo) of reduction entries ko .. ko + 3
+        if (!ADJ) {
+          const uint32_t* b = &Bs[0][0] + 2 * TMV * ko + 2 * r;
+          x0 = *reinterpret_cast<const uint2*>(b);
+          x1 = *reinterpret_cast<const uint2*>(b + 2 * TMV);
+          x2 = *reinterpret_cast<const uint2*>(b + 4 * TMV);
+          x3 = *reinterpret_cast<const uint2*>(b + 6 * TMV);
+        } else {
+          const uint32_t* b = &Bs[0][0] + 32 * r;
+          const int sw = (r >> 1) & 7;
+          const uint4 u = *reinterpret_cast<const uint4*>(b + 4 * ((ko >> 1) ^ sw));
+          const uint4 v = *reinterpret_cast<const uint4*>(b + 4 * (((ko >> 1) + 1) ^ sw));
+          x0 = make_uint2(u.x, u.y);
+          x1 = make_uint2(u.z, u.w);
+          x2 = make_uint2(v.x, v.y);
+          x3 = make_uint2(v.z, v.w);
+        }
+        bh[c] = embed(make_uint4(x0.x, x1.x, x2.x, x3.x));
+        bl[c] = embed(make_uint4(x0.y, x1.y, x2.y, x3.y));
+      }
+      // consecutive instructions go to different accumulator tiles
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
+    }
+  };
+  if (Q > 0) {  // (uniform) an empty reduction leaves the sums at zero
+    const int nch = (Q + KCH - 1) / KCH;
+    issue(As0, Bs0, 0);
+    issue(As1, Bs1, KCH);
+    __builtin_amdgcn_s_waitcnt(vm_lgkm0(DS::NI));  // chunk 0 loaded
+    __builtin_amdgcn_s_barrier();
+    issue(As2, Bs2, 2 * KCH);
+    // chunk q in buffer q % 3: sum it, wait until chunk q + 1 has loaded (q + 2
+    // in flight) and every wave is past its reads, then refill it with q + 3
+    auto step = [&](uint32_t (*As)[TNV * KCH], uint32_t (*Bs)[TMV * KCH], int q) __attribute__((always_inline)) {
+      compute(As, Bs);
+      __builtin_amdgcn_s_waitcnt(vm_lgkm0(DS::NI));
+      __builtin_amdgcn_s_barrier();
+      issue(As, Bs, (q + 3) * KCH);
+    };
+    for (int q = 0; q < nch; q += 3) {
+      step(As0, Bs0, q);
+      if (q + 1 < nch) step(As1, Bs1, q + 1);
+      if (q + 2 < nch) step(As2, Bs2, q + 2);
+    }
+    // no LDS write may be in flight when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(vm_lgkm0(0));
+  }
+  if (flags & kOutSplit)
+    store_out_split<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
+  else
+    store_out<ADJ, RT, CT>(d, R, r0, n0, acc, wn, wm, out, ld_out, nrhs, scale);
 }
 
 // Kernel variants: Shape<TNV, TMV, NTH, RT, CT, PF, DB>.
@@ -707,6 +1063,11 @@ using B3 = Shape<128, 128, 256, 2, 4, true, false>;
 using B4 = Shape<128, 64, 256, 2, 2, true, true>;
 using B5 = Shape<256, 128, 512, 2, 4, true, true>;
 using B6 = Shape<128, 128, 256, 2, 4, true, true>;
+// split input state (k_stage_bf16x3_dma; the PF / DB flags are not used)
+using D0 = Shape<256, 128, 512, 2, 4, true, true>;
+using D1 = Shape<128, 128, 256, 2, 4, true, true>;
+using D2 = Shape<128, 64, 256, 2, 2, true, true>;
+using D3 = Shape<64, 64, 256, 1, 2, true, true>;
 
 struct VariantDims {
   int tnv, tmv, nth;
@@ -716,7 +1077,15 @@ constexpr VariantDims dims_of() {
   return {S::TNV, S::TMV, S::NTH};
 }
 
-VariantDims variant_dims(int prec, int v) {
+VariantDims variant_dims(int prec, bool in_split, int v) {
+  if (in_split) {
+    switch (v) {
+      case 0: return dims_of<D0>();
+      case 1: return dims_of<D1>();
+      case 2: return dims_of<D2>();
+      default: return dims_of<D3>();
+    }
+  }
   if (prec == MBF_C64) {
     switch (v) {
       case 0: return dims_of<F0>();
@@ -752,18 +1121,28 @@ bool use_mfma(const DevPart&, int, int64_t nrhs, int prec) {
 }
 
 // ------------------------------------------------------------------ autotuner
-// Variant choice per (precision, direction, output-rows bucket, reduction
-// bucket, RHS tiles).  Filled by autotune_stage (timing every variant on the
-// stage's real shape) and optionally persisted as text lines
-// "prec adj rb qb nb variant" in the file named by MBF_TUNE_FILE.
+// Variant choice per (kernel family, direction, output-rows bucket, reduction
+// bucket, RHS tiles); the family is the precision, plus 16 for the split-BF16
+// kernels of split input states.  Filled by autotune_stage (timing every
+// variant on the stage's real shape) and optionally persisted as text lines
+// "family adj rb qb nb variant" in the file named by MBF_TUNE_FILE.
 namespace {
 using TuneKey = std::tuple<int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
 bool g_tune_loaded = false;
 
-TuneKey tune_key(int prec, bool adj, int R, int Q, int nrhs) {
-  return TuneKey{prec, adj ? 1 : 0, (R + 63) / 64, (Q + 63) / 64, (nrhs + kTuneRhs - 1) / kTuneRhs};
+constexpr int kSplitFamily = 16;
+// Key family of the split-state choice (see split_choice).
+constexpr int kSplitChoice = 64;
+inline int family(int prec, bool in_split) { return prec + (in_split ? kSplitFamily : 0); }
+inline int family_variants(int fam) {
+  return fam >= kSplitFamily ? num_variants(fam - kSplitFamily, true) : num_variants(fam, false);
+}
+
+TuneKey tune_key(int prec, bool in_split, bool adj, int R, int Q, int nrhs) {
+  return TuneKey{family(prec, in_split), adj ? 1 : 0, (R + 63) / 64, (Q + 63) / 64,
+                 (nrhs + kTuneRhs - 1) / kTuneRhs};
 }
 
 void load_tune_file_locked() {
@@ -775,34 +1154,66 @@ void load_tune_file_locked() {
   if (!f) return;
   int a, b, c, d, e, v;
   while (std::fscanf(f, "%d %d %d %d %d %d", &a, &b, &c, &d, &e, &v) == 6)
-    if (v >= 0 && v < num_variants(a)) g_tune[TuneKey{a, b, c, d, e}] = v;
+    if ((a == MBF_C64 || a == MBF_C64_SPLIT_BF16 || a == MBF_C64_SPLIT_BF16 + kSplitFamily) && v >= 0 &&
+        v < family_variants(a))
+      g_tune[TuneKey{a, b, c, d, e}] = v;
+    else if (a == kSplitChoice + MBF_C64_SPLIT_BF16 && (v == 0 || v == 1))
+      g_tune[TuneKey{a, b, c, d, e}] = v;
   std::fclose(f);
 }
 }  // namespace
 
-int tuned_variant(int prec, bool adj, int R, int Q, int nrhs) {
+int tuned_variant(int prec, bool in_split, bool adj, int R, int Q, int nrhs) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   load_tune_file_locked();
-  auto it = g_tune.find(tune_key(prec, adj, R, Q, nrhs));
+  auto it = g_tune.find(tune_key(prec, in_split, adj, R, Q, nrhs));
   if (it != g_tune.end()) return it->second;
-  if (const char* e = std::getenv("MBF_STAGE_VARIANT")) {
+  if (const char* e = std::getenv("MBF_STAGE_VARIANT")) {  // taken modulo the family's variant count
     const int v = std::atoi(e);
-    if (v >= 0 && v < num_variants(prec)) return v;
+    if (v >= 0) return v % num_variants(prec, in_split);
   }
   // Untuned defaults: the small FP32 tile; for BF16 x3 the double-buffered
   // 256 x 128 tile when the right-hand sides fill it, the 128 x 64 one for
   // mid-size batches, the 64 x 64 one for small batches.
   if (prec == MBF_C64) return 0;
+  if (in_split) return nrhs >= 192 ? 0 : nrhs > 64 ? 2 : 3;
   return nrhs >= 192 ? 5 : nrhs > 64 ? 4 : 0;
+}
+
+namespace {
+TuneKey split_key(int prec, int64_t rows, int nrhs) {
+  return TuneKey{kSplitChoice + prec, 0, (int)(rows >> 16), 0, (nrhs + kTuneRhs - 1) / kTuneRhs};
+}
+}  // namespace
+
+int split_choice(int prec, int64_t rows, int nrhs) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file_locked();
+  auto it = g_tune.find(split_key(prec, rows, nrhs));
+  return it == g_tune.end() ? -1 : it->second;
+}
+
+void set_split_choice(int prec, int64_t rows, int nrhs, bool on) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file_locked();
+  const TuneKey k = split_key(prec, rows, nrhs);
+  g_tune[k] = on ? 1 : 0;
+  if (const char* path = std::getenv("MBF_TUNE_FILE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                   std::get<4>(k), on ? 1 : 0);
+      std::fclose(f);
+    }
+  }
 }
 
 template <bool ADJ>
 static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const BlockDesc* blk, const void* W,
                            const float2* x, int64_t ld_in, float2* y, int64_t ld_out, int nrhs, const float* scale,
-                           int mtiles, int ntiles, int64_t total) {
+                           int mtiles, int ntiles, int64_t total, int flags) {
 #define MBF_LAUNCH(KER, WT, S)                                                                            \
   hipLaunchKernelGGL((KER<ADJ, S>), grid, dim3(S::NTH), 0, st, blk, reinterpret_cast<const WT*>(W), x, ld_in, \
-                     y, ld_out, nrhs, scale, mtiles, ntiles, total)
+                     y, ld_out, nrhs, scale, mtiles, ntiles, total, flags)
   if (prec == MBF_C64) {
     switch (v) {
       case 0: MBF_LAUNCH(k_stage_f32, float2, F0); break;
@@ -816,6 +1227,13 @@ static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const Blo
       case 8: MBF_LAUNCH(k_stage_f32_3m, float2, G8); break;
       case 9: MBF_LAUNCH(k_stage_f32, float2, F9); break;
       default: MBF_LAUNCH(k_stage_f32, float2, F10); break;
+    }
+  } else if (flags & kInSplit) {
+    switch (v) {
+      case 0: MBF_LAUNCH(k_stage_bf16x3_dma, uint2, D0); break;
+      case 1: MBF_LAUNCH(k_stage_bf16x3_dma, uint2, D1); break;
+      case 2: MBF_LAUNCH(k_stage_bf16x3_dma, uint2, D2); break;
+      default: MBF_LAUNCH(k_stage_bf16x3_dma, uint2, D3); break;
     }
   } else {
     switch (v) {
@@ -833,13 +1251,19 @@ static void launch_variant(int prec, int v, dim3 grid, hipStream_t st, const Blo
 
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const BlockDesc* blk, const void* W,
                         const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs, const float* scale,
-                        hipStream_t st, int force_variant) {
+                        hipStream_t st, bool in_split, bool out_split, int force_variant) {
   const int Rmax = adj ? P.max_K[s] : P.max_M[s];
   const int Qmax = adj ? P.max_M[s] : P.max_K[s];
   if (prec != MBF_C64 && prec != MBF_C64_SPLIT_BF16) return {MBF_ERR_UNSUPPORTED, "no MFMA stage kernel"};
   if (nrhs < 1) return {MBF_ERR_INVALID_ARG, "MFMA stage: nrhs < 1"};
-  const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, adj, Rmax, Qmax, nrhs);
-  const VariantDims vd = variant_dims(prec, v);
+  if ((in_split || out_split) && prec != MBF_C64_SPLIT_BF16)
+    return {MBF_ERR_INVALID_ARG, "MFMA stage: split state outside the split-BF16 precision"};
+  // Offsets of the split-input kernel's LDS loads are 32-bit byte offsets
+  // within the 64 state columns of a wave.
+  if (in_split && ld_in >= ((int64_t)1 << 23)) return {MBF_ERR_UNSUPPORTED, "MFMA stage: split state too tall"};
+  const int v = force_variant >= 0 ? force_variant : tuned_variant(prec, in_split, adj, Rmax, Qmax, nrhs);
+  if (v < 0 || v >= num_variants(prec, in_split)) return {MBF_ERR_INVALID_ARG, "MFMA stage: no such variant"};
+  const VariantDims vd = variant_dims(prec, in_split, v);
   const int mtiles = std::max(1, (Rmax + vd.tmv - 1) / vd.tmv);
   const int ntiles = (nrhs + vd.tnv - 1) / vd.tnv;
   const int64_t total = (int64_t)P.nblk[s] * mtiles * ntiles;
@@ -847,12 +1271,13 @@ Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const Block
   if (grid > INT32_MAX) return {MBF_ERR_UNSUPPORTED, "stage grid too large"};
   const float2* x = reinterpret_cast<const float2*>(in);
   float2* y = reinterpret_cast<float2*>(out);
+  const int flags = (in_split ? kInSplit : 0) | (out_split ? kOutSplit : 0);
   if (adj)
     launch_variant<true>(prec, v, dim3((unsigned)grid), st, blk, W, x, ld_in, y, ld_out, nrhs, scale, mtiles, ntiles,
-                         total);
+                         total, flags);
   else
     launch_variant<false>(prec, v, dim3((unsigned)grid), st, blk, W, x, ld_in, y, ld_out, nrhs, scale, mtiles, ntiles,
-                          total);
+                          total, flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return {MBF_ERR_HIP, std::string("stage launch: ") + hipGetErrorString(e)};
   return {MBF_OK, ""};
@@ -862,9 +1287,9 @@ Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adj, const Block
 
 namespace mbf {
 
-Error autotune_stage(const DevPart& P, int s, int prec, bool adj, const BlockDesc* blk, const void* W,
-                     const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs, hipStream_t st,
-                     int* chosen, float* best_ms) {
+Error autotune_stage(const DevPart& P, int s, int prec, bool in_split, bool adj, const BlockDesc* blk,
+                     const void* W, const void* in, int64_t ld_in, void* out, int64_t ld_out, int nrhs,
+                     hipStream_t st, int* chosen, float* best_ms) {
   const int Rmax = adj ? P.max_K[s] : P.max_M[s];
   const int Qmax = adj ? P.max_M[s] : P.max_K[s];
   hipEvent_t e0, e1;
@@ -876,12 +1301,16 @@ Error autotune_stage(const DevPart& P, int s, int prec, bool adj, const BlockDes
   int best = -1;
   float bt = 0.f;
   Error err{MBF_OK, ""};
-  for (int v = 0; v < num_variants(prec) && err.st == MBF_OK; ++v) {
-    err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, v);
+  // split-BF16 stages write a split state except the last one; time that
+  const bool out_split = prec == MBF_C64_SPLIT_BF16;
+  for (int v = 0; v < num_variants(prec, in_split) && err.st == MBF_OK; ++v) {
+    err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, in_split, out_split,
+                            v);
     if (err.st != MBF_OK) break;
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < 2 && err.st == MBF_OK; ++r)
-      err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, v);
+      err = launch_stage_mfma(P, s, prec, adj, blk, W, in, ld_in, out, ld_out, nrhs, nullptr, st, in_split,
+                              out_split, v);
     (void)hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) {
       err = {MBF_ERR_HIP, "autotune timing"};
@@ -900,7 +1329,7 @@ Error autotune_stage(const DevPart& P, int s, int prec, bool adj, const BlockDes
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     load_tune_file_locked();
-    const TuneKey k = tune_key(prec, adj, Rmax, Qmax, nrhs);
+    const TuneKey k = tune_key(prec, in_split, adj, Rmax, Qmax, nrhs);
     g_tune[k] = best;
     if (const char* path = std::getenv("MBF_TUNE_FILE")) {
       if (FILE* f = std::fopen(path, "a")) {

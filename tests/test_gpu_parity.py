@@ -249,6 +249,23 @@ def test_every_stage_kernel_variant_is_exact(variant, prec, monkeypatch):
     _check_both(F, bf, n * n, n * n, 300, prec, seed=variant)
 
 
+def test_split_bf16_state_paths_agree(monkeypatch):
+    """Split-BF16 applies pass the state between stages either split (hi | lo
+    words, read by the split-input kernels) or in FP32 (each stage splits its
+    input): both split the same FP32 values and sum the same products in the
+    same order, so they agree bit for bit, and meet the bar, in both
+    directions.  300 right-hand sides end in a ragged tile."""
+    n = 32
+    bf = _dft_oracle(n, 2, 1e-6)
+    F = _import(bf, ["bf16x3"])
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("MBF_BF16_SPLIT_STATE", mode)
+        out[mode] = _check_both(F, bf, n * n, n * n, 300, "bf16x3", seed=11)
+    for a, b in zip(out["1"], out["0"]):
+        assert np.array_equal(a, b)
+
+
 def test_autotune_keeps_results_within_bar():
     n = 32
     bf = _dft_oracle(n, 2, 1e-6)
@@ -279,8 +296,11 @@ def test_adjoint_identity_on_gpu(prec, bound):
 
 def test_autotune_choices_persist_in_tune_file(tmp_path, monkeypatch):
     """mbf_autotune appends one line per tuned stage shape to MBF_TUNE_FILE
-    ("prec adj rows-bucket reduction-bucket rhs-bucket variant"), every
-    variant index valid for its precision."""
+    ("family adj rows-bucket reduction-bucket rhs-bucket variant"; the family
+    is the precision, 18 for the split-BF16 kernels of split input states),
+    every variant index valid for its family, both split-BF16 families tuned,
+    plus one line (family 66, choice 0 or 1) for the split-BF16 choice between
+    split and FP32 states between stages."""
     path = tmp_path / "tune.txt"
     monkeypatch.setenv("MBF_TUNE_FILE", str(path))
     n = 32
@@ -288,11 +308,18 @@ def test_autotune_choices_persist_in_tune_file(tmp_path, monkeypatch):
     F = _import(bf, ["c64", "bf16x3"])
     tuned = F.autotune("c64", 200) + F.autotune("bf16x3", 200)
     assert tuned > 0
-    lines = [l.split() for l in path.read_text().splitlines() if l.strip()]
+    lines = [tuple(map(int, l.split())) for l in path.read_text().splitlines() if l.strip()]
+    choice = [l for l in lines if l[0] == 66]
+    lines = [l for l in lines if l[0] != 66]
     assert len(lines) == tuned
-    for prec_id, adj, rb, qb, nb, v in (tuple(map(int, l)) for l in lines):
-        assert prec_id in (1, 2) and adj in (0, 1) and rb >= 1 and qb >= 1 and nb >= 1
-        assert 0 <= v < (11 if prec_id == 1 else 7)
+    count = {1: 11, 2: 7, 18: 4}
+    fams = set()
+    for fam, adj, rb, qb, nb, v in lines:
+        assert fam in count and adj in (0, 1) and rb >= 1 and qb >= 1 and nb >= 1
+        assert 0 <= v < count[fam]
+        fams.add(fam)
+    assert fams == {1, 2, 18}
+    assert len(choice) == 1 and choice[0][5] in (0, 1)
     _check_both(F, bf, n * n, n * n, 200, "c64", seed=3)
     _check_both(F, bf, n * n, n * n, 200, "bf16x3", seed=4)
 
