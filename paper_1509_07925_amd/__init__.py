@@ -243,11 +243,25 @@ class Factor:
         _check(lib().mbf_workspace_size(self._h, PREC[prec], nrhs, ctypes.byref(b)))
         return b.value
 
+    def _dims(self):
+        # (nx, nxi) of the handle, fixed for its lifetime
+        if getattr(self, "_nx_nxi", None) is None:
+            inf = self.info()
+            self._nx_nxi = (inf.nx, inf.nxi)
+        return self._nx_nxi
+
+    def _ws_size(self, prec, nrhs):
+        cache = self.__dict__.setdefault("_ws_cache", {})
+        key = (prec, nrhs)
+        if key not in cache:
+            cache[key] = self.workspace_size(prec, nrhs)
+        return cache[key]
+
     # -------------------------------------------------------------- apply
     def _run(self, adj, x, out, prec, workspace, stream):
         import torch
-        inf = self.info()
-        nin, nout = (inf.nx, inf.nxi) if adj else (inf.nxi, inf.nx)
+        nx, nxi = self._dims()
+        nin, nout = (nx, nxi) if adj else (nxi, nx)
         vec = x.dim() == 1
         X = x.reshape(-1, 1) if vec else x
         if X.shape[0] != nin or X.stride(0) != 1 or not X.is_cuda:
@@ -261,7 +275,7 @@ class Factor:
         O = out.reshape(-1, 1) if out.dim() == 1 else out
         if O.shape != (nout, nrhs) or O.stride(0) != 1 or O.dtype != want:
             raise ValueError("bad output tensor")
-        need = self.workspace_size(prec, nrhs)
+        need = self._ws_size(prec, nrhs)
         if workspace is None or workspace.numel() * workspace.element_size() < need:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
         ldx = X.stride(1) if nrhs > 1 else nin

@@ -292,62 +292,115 @@ __global__ __launch_bounds__(256) void k_leaf_reconstruct(const LeafDesc* __rest
 }
 
 // Projection onto leaves with many points (the coarse coronas of the
-// multiscale split): one wave per (leaf, output row k, 16 right-hand sides);
-// the lanes stride over the leaf's points and the sums are combined across
-// the wave with shuffles, so a leaf of thousands of points spreads over r
-// waves instead of one workgroup.
+// multiscale split, up to all N points in one leaf), in two passes.  Pass 1:
+// one wave per (leaf, segment of seg points, KRW output rows, 16 right-hand
+// sides); the lanes stride over the segment's points, every gathered state
+// entry serves the wave's KRW rows, and the sums are combined across the wave
+// with shuffles into part[((leaf maxseg + segment) nrhs + n) max_r + k].
+// Pass 2 adds a leaf's segments in order (deterministic) and scales.  With
+// one segment per leaf (part null) pass 1 scales and stores the sums itself.
+template <typename T>
+constexpr int wide_rows() {  // output rows per wave (KRW): 4 in FP32, 2 in FP64 (registers)
+  return sizeof(T) == 4 ? 4 : 2;
+}
+constexpr int kWideSeg = 1024;  // points per segment
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_leaf_project_wide(const LeafDesc* __restrict__ leaves,
                                                            const typename cx<T>::t* __restrict__ F,
                                                            const int32_t* __restrict__ idx,
                                                            const typename cx<T>::t* __restrict__ x,
-                                                           int64_t ldx, typename cx<T>::t* __restrict__ out,
-                                                           int64_t ld_out, int nrhs,
-                                                           const T* __restrict__ scale) {
+                                                           int64_t ldx, typename cx<T>::t* __restrict__ part,
+                                                           typename cx<T>::t* __restrict__ out, int64_t ld_out,
+                                                           const T* __restrict__ scale, int nrhs, int seg,
+                                                           int maxseg, int max_r) {
   using C = typename cx<T>::t;
-  constexpr int NRW = 16;
-  const LeafDesc d = leaves[blockIdx.x];
-  const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (k >= d.r) return;  // whole wave; no workgroup barrier below
+  constexpr int NRW = 16, KRW = wide_rows<T>();
+  const int leaf = blockIdx.x / maxseg, sg = blockIdx.x % maxseg;
+  const LeafDesc d = leaves[leaf];
+  const int p_lo = sg * seg, p_hi = min(d.np, p_lo + seg);
+  const int k0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * KRW;
+  if (p_lo >= d.np || k0 >= d.r) return;  // whole wave; no workgroup barrier below
   const int lane = threadIdx.x & 63;
   const int n0 = blockIdx.z * NRW;
   const int nn = min(NRW, nrhs - n0);
-  const C* Fk = F + d.f_off + (int64_t)k * d.np;
-  C acc[NRW];
+  C acc[KRW][NRW];
 #pragma unroll
-  for (int n = 0; n < NRW; ++n) acc[n] = czero<C>();
+  for (int j = 0; j < KRW; ++j)
+#pragma unroll
+    for (int n = 0; n < NRW; ++n) acc[j][n] = czero<C>();
   // The NRW loads of a point are issued together (right-hand sides past nrhs
-  // read the last one again; their sums are not stored): a guarded load
-  // would wait for its data before the next one is issued.
+  // read the last one again, rows past r read row r - 1; neither is stored):
+  // a guarded load would wait for its data before the next one is issued.
 #pragma unroll 2
-  for (int i = lane; i < d.np; i += 64) {
-    const C f = cconj(Fk[i]);
+  for (int i = p_lo + lane; i < p_hi; i += 64) {
+    C f[KRW];
+#pragma unroll
+    for (int j = 0; j < KRW; ++j) f[j] = cconj(F[d.f_off + (int64_t)min(k0 + j, d.r - 1) * d.np + i]);
     const int64_t p = idx[d.p_off + i];
     C xv[NRW];
 #pragma unroll
     for (int n = 0; n < NRW; ++n) xv[n] = x[(int64_t)min(n0 + n, nrhs - 1) * ldx + p];
 #pragma unroll
-    for (int n = 0; n < NRW; ++n) cfma(acc[n], f, xv[n]);
+    for (int j = 0; j < KRW; ++j)
+#pragma unroll
+      for (int n = 0; n < NRW; ++n) cfma(acc[j][n], f[j], xv[n]);
   }
 #pragma unroll
-  for (int n = 0; n < NRW; ++n)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      acc[n].x += __shfl_xor(acc[n].x, off);
-      acc[n].y += __shfl_xor(acc[n].y, off);
-    }
-  if (lane == 0) {
-    const int32_t row = d.row + k;
-    const T s = scale ? scale[row] : T(1);
+  for (int j = 0; j < KRW; ++j)
 #pragma unroll
     for (int n = 0; n < NRW; ++n)
-      if (n < nn) {
-        C v = acc[n];
-        v.x *= s;
-        v.y *= s;
-        out[(int64_t)(n0 + n) * ld_out + row] = v;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[j][n].x += __shfl_xor(acc[j][n].x, off);
+        acc[j][n].y += __shfl_xor(acc[j][n].y, off);
       }
+  // lane j NRW + n stores (row k0 + j, right-hand side n0 + n)
+  C* pb = part ? part + (int64_t)blockIdx.x * nrhs * max_r : nullptr;
+#pragma unroll
+  for (int j = 0; j < KRW; ++j)
+#pragma unroll
+    for (int n = 0; n < NRW; ++n)
+      if (lane == j * NRW + n && n < nn && k0 + j < d.r) {
+        if (pb) {
+          pb[(int64_t)(n0 + n) * max_r + k0 + j] = acc[j][n];
+        } else {
+          const int32_t row = d.row + k0 + j;
+          const T sc = scale ? scale[row] : T(1);
+          C v = acc[j][n];
+          v.x *= sc;
+          v.y *= sc;
+          out[(int64_t)(n0 + n) * ld_out + row] = v;
+        }
+      }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_project_wide_sum(const LeafDesc* __restrict__ leaves,
+                                                               const typename cx<T>::t* __restrict__ part,
+                                                               typename cx<T>::t* __restrict__ out,
+                                                               int64_t ld_out, int nrhs, int seg, int maxseg,
+                                                               int max_r, const T* __restrict__ scale) {
+  using C = typename cx<T>::t;
+  const LeafDesc d = leaves[blockIdx.x];
+  const int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  const int k = (int)(e % max_r), n = (int)(e / max_r);
+  if (n >= nrhs || k >= d.r) return;
+  const int nseg = (d.np + seg - 1) / seg;
+  const C* pb = part + ((int64_t)blockIdx.x * maxseg * nrhs + n) * max_r + k;
+  // the segment loads are independent: unrolled, they are in flight together
+  C v = czero<C>();
+#pragma unroll 8
+  for (int sg = 0; sg < nseg; ++sg) {
+    const C a = pb[(int64_t)sg * nrhs * max_r];
+    v.x += a.x;
+    v.y += a.y;
   }
+  const int32_t row = d.row + k;
+  const T sc = scale ? scale[row] : T(1);
+  v.x *= sc;
+  v.y *= sc;
+  out[(int64_t)n * ld_out + row] = v;
 }
 
 // Small leaves (at most 16 points and rank 16, e.g. 4 x 4 leaves): one
@@ -661,12 +714,26 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   const bool v_small = P.max_vnp <= kSmallLeaf && P.max_vr <= kSmallLeaf;
   const bool u_small = P.max_unp <= kSmallLeaf && P.max_ur <= kSmallLeaf;
   const unsigned nt64 = (unsigned)((nrhs + 63) / 64);
+  // part: the other state buffer (ws_ld x nrhs entries), free during the projection
   auto project = [&](bool small, int32_t nleaf, int32_t max_np, int32_t max_r, const LeafDesc* lv, const C* Fl,
-                     const int32_t* idx, C* dst, int64_t lddst, const T* sc) {
-    if (!small && max_np > 256)
-      hipLaunchKernelGGL(k_leaf_project_wide<T>, dim3(nleaf, (unsigned)((max_r + 3) / 4), (unsigned)((nrhs + 15) / 16)),
-                         dim3(256), 0, st, lv, Fl, idx, reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
-    else if (small)
+                     const int32_t* idx, C* dst, int64_t lddst, const T* sc, C* part) {
+    if (!small && max_np > 256) {
+      // segments of kWideSeg points when their partial sums fit the buffer,
+      // else one segment per leaf, summed in place
+      int seg = kWideSeg, maxseg = (max_np + kWideSeg - 1) / kWideSeg;
+      const bool two = maxseg > 1 && (int64_t)nleaf * maxseg * max_r <= ws_ld;
+      if (!two) seg = max_np, maxseg = 1;
+      hipLaunchKernelGGL(k_leaf_project_wide<T>,
+                         dim3((unsigned)(nleaf * maxseg),
+                              (unsigned)((max_r + 4 * wide_rows<T>() - 1) / (4 * wide_rows<T>())),
+                              (unsigned)((nrhs + 15) / 16)),
+                         dim3(256), 0, st, lv, Fl, idx, reinterpret_cast<const C*>(in), ldin, two ? part : nullptr,
+                         dst, lddst, sc, ni, seg, maxseg, max_r);
+      if (two)
+        hipLaunchKernelGGL(k_leaf_project_wide_sum<T>,
+                           dim3(nleaf, (unsigned)(((int64_t)max_r * nrhs + 255) / 256)), dim3(256), 0, st, lv, part,
+                           dst, lddst, ni, seg, maxseg, max_r, sc);
+    } else if (small)
       hipLaunchKernelGGL(k_leaf_project_small<T>, dim3(nleaf, nt64), dim3(256), 0, st, lv, Fl, idx,
                          reinterpret_cast<const C*>(in), ldin, dst, lddst, ni, sc);
     else
@@ -696,7 +763,8 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   if (!adj) {
     if (P.n_vleaf > 0) {
       Timed t(pr, st, 0, pidx, 0, prec, 8.0 * P.v_elems * nr, P.v_elems * es + (P.nxi + P.rows[0]) * nr * es);
-      project(v_small, P.n_vleaf, P.max_vnp, P.max_vr, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], m == 0 ? S : nullptr);
+      project(v_small, P.n_vleaf, P.max_vnp, P.max_vr, P.d_vleaf, Vf, P.d_vidx, buf[0], P.ld[0], m == 0 ? S : nullptr,
+              buf[1]);
     }
     for (int s = 0; s < L; ++s) {
       if (P.nblk[s] == 0) continue;
@@ -728,7 +796,7 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 0, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
       project(u_small, P.n_uleaf, P.max_unp, P.max_ur, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L],
-              m == L ? S : nullptr);
+              m == L ? S : nullptr, buf[(L + 1) & 1]);
     }
     for (int s = L - 1; s >= 0; --s) {
       if (P.nblk[s] == 0) continue;
