@@ -849,7 +849,19 @@ struct Builder {
   Builder(const Tree& x, const Tree& w, const mbf_opts& opts, uint32_t pm)
       : xt(x), ot(w), L(x.L), m(x.L / 2), o(opts), mask(pm), tol(opts.tol), rmax(opts.max_rank),
         os(opts.oversample) {
-    budget = (size_t)(opts.device_mem_gb > 0 ? opts.device_mem_gb : 48) << 30;
+    if (opts.device_mem_gb > 0) {
+      budget = (size_t)opts.device_mem_gb << 30;
+    } else {
+      // By default a third of the memory free when this part starts, between
+      // 48 GiB and 128 GiB (less when less is free): bigger batches keep the
+      // one-workgroup-per-pair kernels of the middle level busy, and what is
+      // left holds the level matrices and the factors built so far.
+      size_t fr = 0, tot = 0;
+      const size_t gib = (size_t)1 << 30;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
+      budget = std::min<size_t>(std::max<size_t>(48 * gib, fr / 3), 128 * gib);
+      if (fr > 0) budget = std::min<size_t>(budget, fr / 10 * 9);
+    }
   }
   ~Builder() {
     for (auto& v : pieces)

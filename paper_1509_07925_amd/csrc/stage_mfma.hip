@@ -793,9 +793,10 @@ __device__ __forceinline__ v4i buffer_rsrc(const void* base, uint32_t bytes) {
 // would otherwise make every later LDS read wait for all such loads, leaves
 // the waits to the kernel (explicit s_waitcnt before the barriers that
 // publish a buffer).  The instruction has no register result.
+// The LDS address of a flat pointer into LDS is its low 32 bits (the LDS
+// aperture's base is 4 GiB aligned).
 __device__ __forceinline__ void lds_load_dword(v4i rs, const uint32_t* lds, uint32_t voff, uint32_t soff) {
-  const uint32_t a = __builtin_amdgcn_readfirstlane(
-      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)lds);
+  const uint32_t a = __builtin_amdgcn_readfirstlane((uint32_t)reinterpret_cast<uintptr_t>(lds));
   asm volatile("" : "+s"(soff));  // a register even when the offset is a known constant
   asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, %3 offen lds" ::"s"(a), "v"(voff), "s"(rs), "s"(soff)
                : "memory");
