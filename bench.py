@@ -39,7 +39,9 @@ CONFIGS = {
     # 1024^2 case keeps only the FP32 factors resident
     "fio256ms": dict(kernel="fio", n=256, tol=1e-4, leaf=4, nrhs=16, split="multiscale", adjoint=True),
     "fio1024ms": dict(kernel="fio", n=1024, tol=1e-4, leaf=4, nrhs=16, split="multiscale", adjoint=True,
-                      fp32_only=True),
+                      fp32_only=True, deadline=1140),
+    # served request mix over eight factorizations (see SERVE8)
+    "serve8": dict(serve8=True, deadline=1100),
 }
 DEFAULT_CONFIG = os.environ.get("MBF_BENCH_CONFIG", "dft512")
 
@@ -176,12 +178,17 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--deadline", type=float, default=float(os.environ.get("MBF_BENCH_DEADLINE", "420")),
-                    help="seconds from the start after which optional legs are skipped")
+    ap.add_argument("--deadline", type=float, default=None,
+                    help="seconds from the start after which optional legs are skipped (default: the "
+                         "config's, else MBF_BENCH_DEADLINE, else 420)")
     ap.add_argument("--builder", default="device", choices=["device", "host"])
+    ap.add_argument("--serve-requests", type=int, default=10000, help="serve8: measured requests per load")
+    ap.add_argument("--serve-warmup", type=int, default=500, help="serve8: warm-up requests per load")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.deadline is None:
+        args.deadline = float(CONFIGS[args.config].get("deadline", os.environ.get("MBF_BENCH_DEADLINE", "420")))
     budget = Budget(args.deadline)
     if args.copy_calibration:
         import torch
@@ -208,6 +215,9 @@ def main():
     import paper_1509_07925_amd as mbf
 
     cfg = CONFIGS[args.config]
+    if cfg.get("serve8"):
+        serve8_main(args, budget)
+        return
     n, nrhs = cfg["n"], cfg["nrhs"]
     N = n * n
     dev = torch.device("cuda:0")
@@ -293,8 +303,21 @@ def main():
         u64 = None
 
     u_np = u32.t().contiguous().cpu().numpy().astype(np.complex128).T
+    adj = None
+    if cfg.get("adjoint"):
+        # adjoint of another random input h, and the identity <h, K g> = <K^* h, g>
+        h_host = W.rhs(N, nrhs, seed=2)
+        h = torch.from_numpy(np.ascontiguousarray(h_host.T)).to(dev, torch.complex64).t()
+        v = F.apply_adjoint(h)
+        torch.cuda.synchronize()
+        v_np = v.t().contiguous().cpu().numpy().astype(np.complex128).T
+        lhs, rhs = np.vdot(h_host, u_np), np.vdot(v_np, g_host)
+        out["adjoint_identity_rel"] = float(abs(lhs - rhs) / abs(lhs))
+        log("adjoint identity: %.2e" % out["adjoint_identity_rel"])
+        adj = (h_host, v_np)
+        del h, v
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, x, xi, g_host, u_np, out)
+        out["cpu_baseline"] = cpu_baseline(cfg, x, xi, g_host, u_np, out, adj=adj)
         log("CPU baseline: %s" % out["cpu_baseline"]["sample"])
 
     # ------------------------------------------------------------ optional legs
@@ -366,69 +389,158 @@ def main():
         del g_h, u_h, g_d, u_d
 
     if not args.no_serve and budget.allow("serving", 60):
-        out["serving"] = serve_mix(F, N, dev, budget)
-        log("served at %.0f%% of the measured capacity: p50 %.1f ms p99 %.1f ms" % (
-            100 * out["serving"]["load"], out["serving"]["p50_ms"], out["serving"]["p99_ms"]))
+        out["serving"] = serve_loads([(out["config"]["workload"], F, N)], dev, budget)
 
     out["skipped_legs"] = budget.skipped
     out["wall_s"] = round(time.time() - budget.t0, 1)
     print(json.dumps(out), flush=True)
 
 
-def _serve_run(srv_args, F, N, dev, ins, outs, arrivals):
-    """Submit requests at the given arrival times; per-request latencies (ms)."""
-    import numpy as np
+class _Stream:
+    """A seeded request stream over resident factorizations: request i goes
+    to factorization fac[i] (uniform) with size[i] in 1..32 RHS; inputs are
+    column slices of one random block per factorization, outputs a ring of
+    64 blocks per factorization (the bench never reads them)."""
 
-    import paper_1509_07925_amd as mbf
-    srv = mbf.Server(**srv_args)
+    def __init__(self, facs, dev, count, seed):
+        import numpy as np
+        import torch
+        rng = np.random.default_rng(seed)
+        self.fac = rng.integers(0, len(facs), size=count)
+        self.size = rng.integers(1, 33, size=count)
+        self.facs = facs
+        self.src = [torch.randn((32, N), dtype=torch.complex64, device=dev) for _, _, N in facs]
+        self.ring = [[torch.empty((32, N), dtype=torch.complex64, device=dev) for _ in range(64)]
+                     for _, _, N in facs]
+        torch.cuda.synchronize()
+
+    def request(self, i):
+        k, m = int(self.fac[i]), int(self.size[i])
+        return self.facs[k][1], self.src[k][:m].t(), self.ring[k][i % 64][:m].t()
+
+
+def _serve_run(srv, stream, lo, hi, arrivals):
+    """Submit requests lo..hi-1 at the given arrival times (seconds from the
+    start); per-request latencies (ms) and the wall time to the last completion."""
+    import numpy as np
     ids = []
     t_start = time.perf_counter()
-    for i in range(len(ins)):
-        while time.perf_counter() - t_start < arrivals[i]:
+    for i in range(lo, hi):
+        while time.perf_counter() - t_start < arrivals[i - lo]:
             pass
-        ids.append(srv.submit(F, ins[i], outs[i], ready=False))
+        F, g, u = stream.request(i)
+        ids.append(srv.submit(F, g, u, ready=False))
     srv.drain()
     wall = time.perf_counter() - t_start
     lat = np.array([srv.poll(r)[1] / 1e3 for r in ids])
+    return lat, wall
+
+
+def serve_loads(facs, dev, budget, loads=(0.5, 0.8, 0.95), nreq=1500, warm=200, ncal=600, graphs=True,
+                seed=0, mem_budget=48 << 30):
+    """Served Poisson streams over the resident factorizations (continuous
+    batching through one mbf_server, 4 slots, up to 256 RHS per batch,
+    graph-captured applies when `graphs`): 1..32 RHS per request on a
+    uniformly drawn factorization.  The capacity is measured on a saturated
+    stream (ncal requests queued at once); each load then offers
+    warm + nreq Poisson arrivals at load x capacity, and p50 / p99 are taken
+    over the nreq requests after the warm-up."""
+    import numpy as np
+
+    import mbf_workloads as W
+    import paper_1509_07925_amd as mbf
+    total = ncal + len(loads) * (warm + nreq)
+    stream = _Stream(facs, dev, total, seed)
+    srv = mbf.Server(mem_budget=mem_budget, nslots=4, max_batch_rhs=256, graphs=graphs)
+    res = {"graphs": bool(graphs), "slots": 4, "max_batch_rhs": 256, "mem_budget_gb": round(mem_budget / 2 ** 30, 1),
+           "factorizations": [name for name, _, _ in facs], "request_rhs": "uniform 1..32",
+           "factorization_choice": "uniform", "loads": []}
+    # capacity: the calibration requests queued at once (twice: the first pass
+    # also captures the graphs)
+    for rep in range(2):
+        _, wall = _serve_run(srv, stream, 0, ncal, np.zeros(ncal))
+    capacity = float(np.sum(stream.size[:ncal])) / wall
+    res["capacity_rhs_per_s"] = round(capacity, 1)
+    lo = ncal
+    for li, load in enumerate(loads):
+        rate = load * capacity / float(np.mean(stream.size))
+        arrivals = W.poisson_arrivals(warm + nreq, rate, seed=seed + 1 + li)
+        hi = lo + warm + nreq
+        if arrivals[-1] > budget.left() - 20:
+            budget.skipped.append("serving load %.2f (%.0f s of arrivals, %.0f s left)" % (
+                load, arrivals[-1], budget.left()))
+            lo = hi
+            continue
+        lat, wall = _serve_run(srv, stream, lo, hi, arrivals)
+        sizes = stream.size[lo:hi]
+        lat_m = lat[warm:]
+        res["loads"].append({"load": load, "requests": int(lat_m.size), "warmup_requests": int(warm),
+                             "offered_rhs_per_s": round(load * capacity, 1),
+                             "served_rhs_per_s": round(float(np.sum(sizes)) / wall, 1),
+                             "p50_ms": round(float(np.percentile(lat_m, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat_m, 99)), 3),
+                             "mean_ms": round(float(np.mean(lat_m)), 3)})
+        log("served %s at %.2f of capacity (%.0f RHS/s): p50 %.2f ms p99 %.2f ms" % (
+            "graphs" if graphs else "direct", load, capacity, res["loads"][-1]["p50_ms"],
+            res["loads"][-1]["p99_ms"]))
+        lo = hi
     st = srv.stats()
     srv.close()
-    return lat, wall, st
+    res.update({"batches": int(st["batches"]), "max_concurrent_batches": int(st["max_concurrent_batches"]),
+                "graphs_captured": int(st["graphs_captured"]), "graph_batches": int(st["graph_batches"])})
+    return res
 
 
-def serve_mix(F, N, dev, budget, nreq=1500, warm=200, load=0.8, seed=0):
-    """Served Poisson stream on the resident factorization (continuous
-    batching through mbf_server, 4 slots): 1..32 RHS per request, offered at
-    `load` times the capacity measured on a saturated mixed stream of the
-    same request sizes; p50 / p99 over the requests after a warm-up."""
-    import numpy as np
+# The served mix over eight resident factorizations: the 2D DFT and the FIO
+# of Example 1 at n = 64, 128, 256, 512 (FP32 factors only).
+SERVE8 = [dict(kernel=k, n=n, tol=1e-6 if k == "dft" else 1e-4, leaf=4, split="none" if k == "dft" else "multiscale")
+          for k in ("dft", "fio") for n in (64, 128, 256, 512)]
+
+
+def serve8_main(args, budget):
+    """--config serve8: build the eight factorizations, then serve the same
+    seeded stream with per-kernel launches and with graph launches at loads
+    0.5, 0.8 and 0.95 of each mode's measured capacity (10000 requests after
+    500 warm-up requests per load)."""
     import torch
 
     import mbf_workloads as W
-
-    rng = np.random.default_rng(seed)
-    sizes = rng.integers(1, 33, size=nreq + warm)
-    pool = torch.randn((64, N), dtype=torch.complex64, device=dev)  # request inputs drawn from here
-    outs = [torch.empty((int(k), N), dtype=torch.complex64, device=dev).t() for k in sizes]
-    ins = [pool[: int(k)].t() for k in sizes]
-    torch.cuda.synchronize()
-    srv_args = dict(mem_budget=24 << 30, nslots=4, max_batch_rhs=256)
-    # capacity: every calibration request queued at once
-    ncal = min(300, nreq)
-    _, wall, st = _serve_run(srv_args, F, N, dev, ins[:ncal], outs[:ncal], np.zeros(ncal))
-    capacity = float(np.sum(sizes[:ncal])) / wall
-    rate = load * capacity / float(np.mean(sizes))
-    arrivals = W.poisson_arrivals(nreq + warm, rate, seed=seed)
-    if arrivals[-1] > budget.left() - 20:
-        keep = int(np.searchsorted(arrivals, max(budget.left() - 20, 1.0)))
-        arrivals, ins, outs, sizes = arrivals[:keep], ins[:keep], outs[:keep], sizes[:keep]
-        warm = min(warm, keep // 4)
-    lat, wall, st = _serve_run(srv_args, F, N, dev, ins, outs, arrivals)
-    lat = lat[warm:]
-    return {"requests": int(lat.size), "warmup_requests": int(warm), "load": load,
-            "capacity_rhs_per_s": round(capacity, 1), "offered_rhs_per_s": round(load * capacity, 1),
-            "served_rhs_per_s": round(float(np.sum(sizes)) / wall, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "batches": int(st["batches"]), "max_concurrent_batches": int(st["max_concurrent_batches"])}
+    import paper_1509_07925_amd as mbf
+    dev = torch.device("cuda:0")
+    out = {"metric": "served RHS/s and p50/p99 latency over a Poisson request mix", "value": None,
+           "unit": "RHS/s", "n_gpus": 1, "steps": None, "warmup": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    facs = []
+    t0 = time.time()
+    for c in SERVE8:
+        n = c["n"]
+        x, xi = (W.grid_x_integer(n), W.grid_omega(n)) if c["kernel"] == "dft" else (W.grid_x_unit(n), W.grid_omega(n))
+        t1 = time.time()
+        F = mbf.Factor.build(x, xi, n, kernel=c["kernel"], tol=c["tol"], leaf_side=c["leaf"], split=c["split"],
+                             precs=["c64"], max_rank=4096, builder="device")
+        ws = torch.empty(F.workspace_size("c64", 256), dtype=torch.uint8, device=dev)
+        for w in (32, 64, 256):
+            F.autotune("c64", w, workspace=ws)
+        del ws
+        name = workload_name(dict(c, nrhs=0)).replace("_rhs0", "")
+        log("built %s in %.1f s" % (name, time.time() - t1))
+        facs.append((name, F, n * n))
+    torch.cuda.empty_cache()
+    out["config"] = {"workload": "serve_mix8_dft_fio_n64-512", "factorizations": [f[0] for f in facs],
+                     "setup_s": round(time.time() - t0, 1)}
+    modes = {}
+    for graphs in (False, True):
+        modes["graphs" if graphs else "direct"] = serve_loads(facs, dev, budget, nreq=args.serve_requests,
+                                                              warm=args.serve_warmup, ncal=2000, graphs=graphs)
+    out["serving"] = modes
+    g = modes["graphs"]["loads"]
+    if g:
+        out["value"] = g[-1]["served_rhs_per_s"]
+        out["p50_ms"], out["p99_ms"] = g[-1]["p50_ms"], g[-1]["p99_ms"]
+        out["value_at_load"] = g[-1]["load"]
+    out["skipped_legs"] = budget.skipped
+    out["wall_s"] = round(time.time() - budget.t0, 1)
+    print(json.dumps(out), flush=True)
 
 
 def _cpu_model():
@@ -448,12 +560,14 @@ def _host_cores():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(cfg, x, xi, g, u_gpu, out, reps=5):
+def cpu_baseline(cfg, x, xi, g, u_gpu, out, reps=5, adj=None):
     """Oracle leg: the direct FP64 sum of eq. (kernel) on sampled rows (the
     paper's error estimator and speed-up denominator), with all host cores
     and with one, median of `reps` runs each, scaled to RHS/s over all rows;
     for the DFT also the oracle's FFT closed form (numpy, one core) and the
-    same transform with scipy.fft on all cores."""
+    same transform with scipy.fft on all cores.  With adj = (h, v) (v the
+    library's adjoint of h) also the adjoint's error on 256 sampled Omega
+    points, against the conjugate-transposed kernel columns summed directly."""
     import numpy as np
     import threadpoolctl
 
@@ -466,6 +580,11 @@ def cpu_baseline(cfg, x, xi, g, u_gpu, out, reps=5):
     K = kernels.dft(n) if cfg["kernel"] == "dft" else kernels.fio_radon(n)
     rows = W.sample_rows(N, 256, seed=1)
     out["rel_err_vs_direct_sampled_rows"] = direct.rel_err(u_gpu[rows], direct.direct_rows(K, x, xi, g, rows, block=256))
+    if adj is not None:
+        h, v_gpu = adj
+        cols = W.sample_rows(N, 256, seed=3)
+        v_direct = K(x, xi[cols]).conj().T @ h
+        out["rel_err_adjoint_vs_direct_sampled_cols"] = direct.rel_err(v_gpu[cols], v_direct)
 
     def med(fn):
         ts = []

@@ -121,7 +121,9 @@ int mbf_kernel_fio(void* user, int64_t m, const int64_t* rows, int64_t k, const 
  *              which resolve singular values down to about 1e-8 of the
  *              largest).  Otherwise MBF_ERR_UNSUPPORTED.
  *   device_mem_gb  MBF_BUILD_DEVICE: bound on the builder's scratch memory
- *              (GB; 0 = 48).  The finished factors are not counted.       */
+ *              (GiB; 0 = a third of the device memory free when each part's
+ *              build starts, between 48 and 128 GiB, at most 90% of what is
+ *              free).  The finished factors are not counted.               */
 typedef enum { MBF_BUILD_HOST = 0, MBF_BUILD_DEVICE = 1 } mbf_builder;
 typedef struct {
   double tol;
@@ -160,6 +162,39 @@ typedef struct {
 mbf_status mbf_build(int32_t dim, int64_t nx, const double* x, int64_t nxi, const double* xi,
                      mbf_entry_cb cb, void* user, const mbf_opts* opts, void* stream,
                      mbf_factor* out);
+
+/* Black box of build case (i) (Section 2.3: fast products with K and K^*
+ * are available).  adjoint = 0: out = K in, with in nxi x ncols and out
+ * nx x ncols; adjoint = 1: out = K^* in, with in nx x ncols and out
+ * nxi x ncols.  Host buffers of interleaved complex128, column-major with
+ * the row count as leading dimension, valid during the call only; point
+ * order as given to mbf_build_matvec.  Return 0 on success; any other
+ * value aborts the build with MBF_ERR_CALLBACK.  Called from one host
+ * thread at a time. */
+typedef int (*mbf_matvec_cb)(void* user, int32_t adjoint, int64_t ncols, const double* in, double* out);
+
+/* Build case (i) (Section 2.3; PBF-m of Section 3.2, MBF-m of Section 4.2):
+ * the factorization of a K known only through mv.  Trees, splits and the
+ * recursive factorizations of U^h and V^h are those of mbf_build; every
+ * middle-level block K_{A,B} is factored by the SVD via random
+ * matrix-vector products (Section 2.1, first option) from K C^P_B and
+ * K^* R^P_A, where C^P_B (R^P_A) holds Gaussian entries on the points of the
+ * Omega node B (X node A) and zeros elsewhere: one product with K per
+ * middle-level Omega node, one with K^* per middle-level X node, all of
+ * them taken before the factorization.  Bases of at most max_rank columns
+ * come from pivoted QR of the products; the middle matrix
+ * M = pinv(R^* Q_col) (R^* K C) pinv(Q_row^* C) from two least-squares
+ * solves; its SVD truncated by tol.  The dense center of the multiscale
+ * split is K applied to its unit vectors.
+ *   probes  NULL: Gaussian probes drawn from opts->seed; else q =
+ *           max_rank + oversample columns of C (nxi x q) followed by those
+ *           of R (nx x q), interleaved complex128, column-major (host,
+ *           read during the call).  oversample must be >= 1.
+ * opts->builder must be MBF_BUILD_HOST (else MBF_ERR_UNSUPPORTED).  Other
+ * errors as mbf_build. */
+mbf_status mbf_build_matvec(int32_t dim, int64_t nx, const double* x, int64_t nxi, const double* xi,
+                            mbf_matvec_cb mv, void* user, const mbf_opts* opts, const double* probes,
+                            void* stream, mbf_factor* out);
 
 /* Import an already built factorization: the factors of eq. (gbf) as host
  * arrays (FP64), read during the call only.  Used to apply factorizations
@@ -320,6 +355,15 @@ mbf_status mbf_profile_end(mbf_factor f, mbf_launch_record* out, int32_t cap, in
  * next batches as slots and memory free up.  When several queued requests
  * together exceed the pool, the later ones wait for a following batch; only
  * a request that cannot fit the whole budget on its own fails.
+ * flags: 0, or MBF_SERVER_GRAPHS: each slot keeps one fixed region of the
+ * pool for its staging blocks and workspace (sized for the largest batch it
+ * has run; grown on demand, and the regions of idle slots are given back
+ * when the pool cannot otherwise hold a growth), and runs each batch's apply
+ * as one launch of a HIP graph captured once per (factor, precision, batch
+ * width) on the slot's stream; batch widths are rounded up to a power of two
+ * of at least 16 columns, within max_batch_rhs (the padding columns compute
+ * results that are never read).  Without it every batch enqueues the apply's
+ * kernels one by one into a reservation of its own.  Results are the same.
  *   submit: u = K g for one request (device pointers owned by the caller,
  *           unchanged until the request completes); returns its id.
  *           Readiness: the server's streams do not follow the caller's
@@ -341,15 +385,18 @@ mbf_status mbf_profile_end(mbf_factor f, mbf_launch_record* out, int32_t cap, in
  *           MBF_ERR_HIP if any batch failed since the server was created.
  *   stats:  p50 / p99 / mean latency over the last 2^20 successful requests,
  *           requests, RHS, batches, the largest number of batches in flight
- *           at once, wall time first submit -> last completion.
+ *           at once, graphs captured and batches run as a graph launch, wall
+ *           time first submit -> last completion.
  * A factor must outlive every request that names it.  Submit, poll, drain
  * and stats may be called from any host thread. */
 typedef struct mbf_server_s* mbf_server;
 typedef struct {
-  int64_t requests, rhs, batches, max_concurrent_batches;
+  int64_t requests, rhs, batches, max_concurrent_batches, graphs_captured, graph_batches;
   double p50_us, p99_us, mean_us, wall_s;
 } mbf_server_stats_t;
-mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, mbf_server* out);
+#define MBF_SERVER_GRAPHS 1u
+mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, uint32_t flags,
+                             mbf_server* out);
 mbf_status mbf_server_submit(mbf_server s, mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg,
                              void* u, int64_t ldu, void* ready_event, uint64_t* id);
 mbf_status mbf_server_poll(mbf_server s, uint64_t id, int32_t* done, double* latency_us);

@@ -20,6 +20,10 @@ Follows Section 2 of the paper, in its order and notation:
 Pair bookkeeping ("stage s"): pairs (A at X-level s, B at Omega-level L-s).
 Stage 0 holds one vector per Omega leaf, stage L one per X leaf.
 
+Middle level from entries (case (ii): exact SVD or random sampling) or,
+when K is known only through fast products with K and K^*, from products
+with zero-padded Gaussian probes (case (i), Section 2.3; PBF-m / MBF-m).
+
 PBF (Section 3.2): the Omega tree is built over p = polar(xi); entries
 stay K(x, xi).  MSBF (Section 4.2, eq. (msumd), eq. (f1)): a sum over
 coronas of butterfly factorizations plus a dense center block.
@@ -50,12 +54,20 @@ class Butterfly:
     # ------------------------------------------------------------------ build
     @classmethod
     def build(cls, entries, x, xi_tree_pts, xbox, obox, depth, tol, rmax,
-              method="sampling", seed=0, nxi=None):
+              method="sampling", seed=0, nxi=None, matvec=None, probes=None):
         """Build from an entry function ``entries(I, J) = K(x[I], xi[J])``.
 
         x : X points used for the X tree; xi_tree_pts : Omega points in the
         coordinates the Omega tree partitions (xi itself, or polar(xi));
         xbox / obox : (lo, side) of the root squares; depth : L.
+
+        method "exact" (dense SVD of each middle block), "sampling" (SVD via
+        random sampling, case (ii)) or "matvec" (case (i), Section 2.3): the
+        middle blocks are known only through ``matvec(adjoint, block)``,
+        which returns K block (block: nxi x q) or K^* block (block: nx x q),
+        applied to the zero-padded Gaussian probes C^P_B and R^P_A taken
+        from ``probes = (C, R)`` (nxi x q and nx x q: C_B = C[B], R_A = R[A]).
+        ``entries`` is not used then.
         """
         rng = np.random.default_rng(seed)
         xt = trees.QuadTree(x, xbox[0], xbox[1], depth)
@@ -63,6 +75,22 @@ class Butterfly:
         self = cls(xt, ot, x.shape[0], xi_tree_pts.shape[0])
         L, m = self.L, self.m
         self.rank = [dict() for _ in range(L + 1)]
+
+        if method == "matvec":
+            # K C^P_B holds K_{A,B} C_B for every A; K^* R^P_A holds
+            # K_{A,B}^* R_A for every B (Section 2.3, case (i)).
+            Cp, Rp = probes
+            KC, KsR = {}, {}
+            for b in ot.nodes[L - m]:
+                ib = ot.points(L - m, int(b))
+                pad = np.zeros((self.nxi, Cp.shape[1]), complex)
+                pad[ib] = Cp[ib]
+                KC[int(b)] = matvec(False, pad)
+            for a in xt.nodes[m]:
+                ia = xt.points(m, int(a))
+                pad = np.zeros((self.nx, Rp.shape[1]), complex)
+                pad[ia] = Rp[ia]
+                KsR[int(a)] = matvec(True, pad)
 
         # Middle level factorization (Section 2.3), form 1.
         U, V = {}, {}
@@ -73,6 +101,8 @@ class Butterfly:
                 a_, b_ = int(a), int(b)
                 if method == "exact":
                     U0, s, V0 = lowrank.svd_trunc(entries(ia, ib), tol, rmax)
+                elif method == "matvec":
+                    U0, s, V0 = lowrank.svd_matvec(KC[b_][ia], KsR[a_][ib], Cp[ib], Rp[ia], tol, rmax)
                 else:
                     U0, s, V0 = lowrank.svd_sampling(
                         lambda I, J: entries(ia[I], ib[J]), ia.size, ib.size, tol, rmax, rng)
@@ -285,31 +315,59 @@ def corona_depth(n, t, leaf_side=1):
     return max(2 * ((L - t) // 2), 0)
 
 
+def _restrict(matvec, idx, nxi):
+    """The black box of K restricted to the Omega columns idx: K[:, idx] B
+    is K applied to B padded with zeros, (K[:, idx])^* B the rows idx of K^* B."""
+    def mv(adjoint, block):
+        if adjoint:
+            return matvec(True, block)[idx]
+        full = np.zeros((nxi, block.shape[1]), complex)
+        full[idx] = block
+        return matvec(False, full)
+    return mv
+
+
 def build_multiscale(K, x, xi, n, xbox, tol, rmax, center_side=16, leaf_side=1,
-                     method="sampling", seed=0):
-    """MSBF build: corona split, one butterfly per corona, dense center."""
+                     method="sampling", seed=0, matvec=None, probes=None):
+    """MSBF build: corona split, one butterfly per corona, dense center.
+
+    method "matvec" (MBF-m): K is not used; each corona's butterfly is built
+    from ``matvec`` restricted to its columns (probes restricted likewise)
+    and the dense center K_C is K applied to the unit vectors of Omega_C."""
     cor, center = trees.coronas(xi, n, center_side)
     parts = []
     for t, a, idx in cor:
         Lt = corona_depth(n, t, leaf_side)
         xs = xi[idx]
-        ent = (lambda xs_: (lambda I, J: K(x[I], xs_[J])))(xs)
-        bf = Butterfly.build(ent, x, xs, xbox, ((-a, -a), 2 * a), Lt, tol, rmax,
-                             method=method, seed=seed + 101 * t, nxi=idx.size)
+        if method == "matvec":
+            bf = Butterfly.build(None, x, xs, xbox, ((-a, -a), 2 * a), Lt, tol, rmax, method="matvec",
+                                 nxi=idx.size, matvec=_restrict(matvec, idx, xi.shape[0]),
+                                 probes=(probes[0][idx], probes[1]))
+        else:
+            ent = (lambda xs_: (lambda I, J: K(x[I], xs_[J])))(xs)
+            bf = Butterfly.build(ent, x, xs, xbox, ((-a, -a), 2 * a), Lt, tol, rmax,
+                                 method=method, seed=seed + 101 * t, nxi=idx.size)
         parts.append((t, idx, bf))
-    KC = K(x, xi[center])
+    if method == "matvec":
+        E = np.zeros((xi.shape[0], center.size), complex)
+        E[center, np.arange(center.size)] = 1.0
+        KC = matvec(False, E)
+    else:
+        KC = K(x, xi[center])
     return Multiscale(parts, center, KC, x.shape[0], xi.shape[0])
 
 
-def build_polar(K, x, xi, n, xbox, depth, tol, rmax, method="sampling", seed=0):
-    """PBF build (Section 3.2): Omega tree over p = polar(xi) in [0,1]^2."""
+def build_polar(K, x, xi, n, xbox, depth, tol, rmax, method="sampling", seed=0, matvec=None, probes=None):
+    """PBF build (Section 3.2): Omega tree over p = polar(xi) in [0,1]^2
+    (PBF-m with method "matvec": K is not used)."""
     p = trees.polar_map(xi, n)
-    ent = lambda I, J: K(x[I], xi[J])
+    ent = None if K is None else (lambda I, J: K(x[I], xi[J]))
     return Butterfly.build(ent, x, p, xbox, ((0.0, 0.0), 1.0), depth, tol, rmax,
-                           method=method, seed=seed)
+                           method=method, seed=seed, matvec=matvec, probes=probes)
 
 
-def build_plain(K, x, xi, xbox, obox, depth, tol, rmax, method="sampling", seed=0):
+def build_plain(K, x, xi, xbox, obox, depth, tol, rmax, method="sampling", seed=0, matvec=None, probes=None):
     """BF build on the original Omega (Section 2)."""
-    ent = lambda I, J: K(x[I], xi[J])
-    return Butterfly.build(ent, x, xi, xbox, obox, depth, tol, rmax, method=method, seed=seed)
+    ent = None if K is None else (lambda I, J: K(x[I], xi[J]))
+    return Butterfly.build(ent, x, xi, xbox, obox, depth, tol, rmax, method=method, seed=seed,
+                           matvec=matvec, probes=probes)

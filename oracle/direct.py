@@ -75,6 +75,32 @@ def linear_phase_ifft(n, g):
     return u[:, 0] if vec else u
 
 
+class ComposedFIO:
+    """Example 2 of Section 3.3 (eq. (example2mfio), eq. (KFK)): the
+    composition K~ = K F K of the Example 1 FIO K with the discrete Fourier
+    transform F[eta, y] = exp(-2 pi i y . eta) (y in the unit grid X, eta in
+    the integer grid Omega), evaluated directly: K and F are formed densely
+    from their definitions in FP64 and applied one after the other.
+    ``apply(g)`` = K F K g, ``adjoint(h)`` = K^* F^* K^* h."""
+
+    def __init__(self, K, x, xi):
+        x = np.asarray(x, dtype=np.float64)
+        xi = np.asarray(xi, dtype=np.float64)
+        self.K = K(x, xi)
+        self.F = np.exp(-2j * np.pi * (np.outer(xi[:, 0], x[:, 0]) + np.outer(xi[:, 1], x[:, 1])))
+
+    def apply(self, g):
+        return self.K @ (self.F @ (self.K @ np.asarray(g, dtype=np.complex128)))
+
+    def adjoint(self, h):
+        Kh = self.K.conj().T
+        return Kh @ (self.F.conj().T @ (Kh @ np.asarray(h, dtype=np.complex128)))
+
+    def matvec(self, adjoint, block):
+        """The black box of case (i): K~ block or K~^* block."""
+        return self.adjoint(block) if adjoint else self.apply(block)
+
+
 def rel_err(a, b):
     """sqrt(sum |a-b|^2 / sum |b|^2) (the estimator of Sections 3.3 / 4.3)."""
     a = np.asarray(a)

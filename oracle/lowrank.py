@@ -3,6 +3,10 @@
 Truncation rule (the paper fixes a rank r; tolerance reading): keep the
 singular values sigma_k > tol * sigma_1, at most ``rmax`` of them.
 
+SVD via random matrix-vector products (Section 2.1, first option) works
+from products with Gaussian matrices only; SVD via random sampling (second
+option) from sampled entries.
+
 Three forms of a truncated SVD Z ~ U0 S0 V0^* (eq. (lowrank1)-(lowrank3)):
   form 1: U = U0 S0, S = S0^{-1}, V^* = S0 V0^*
   form 2: U = U0 S0, V^* = V0^*
@@ -93,6 +97,43 @@ def svd_sampling(entries, m, n, tol, rmax, rng, q=None, max_rounds=3, oversample
     Icol = np.union1d(reps_c, rng.choice(n, size=qc_, replace=False))
     Zs = entries(Irow, Icol)
     M = np.linalg.pinv(Qc[Irow]) @ Zs @ np.linalg.pinv(Qr[Icol].conj().T)
+    Um, sm, Vmh = np.linalg.svd(M, full_matrices=False)
+    r = _rank(sm, tol, rmax)
+    return Qc @ Um[:, :r], sm[:r], Qr @ Vmh[:r].conj().T
+
+
+def svd_matvec(ZC, ZsR, C, R, tol, rmax):
+    """Approximate truncated SVD via random matrix-vector products
+    (Section 2.1, first option; Section 2.3, case (i)).
+
+    Inputs are the products with Gaussian matrices C (n x q) and R (m x q):
+    ZC = Z C (m x q) and ZsR = Z^* R (n x q); Z itself is never formed.
+    The probes carry q = r + k columns for the rank r = ``rmax`` and an
+    oversampling k > 0.  Steps, in the paper's order:
+      1. pivoted QR of ZC and of Z^*R: orthonormal Q_col (m x kc) and
+         Q_row (n x kr), kc, kr <= r, spanning the column and row spaces
+         (columns kept while the pivot magnitude exceeds tol * 1e-2 of the
+         first, at most r of them: the k extra probe columns keep the
+         solves of step 2 overdetermined);
+      2. M = pinv(R^* Q_col) (R^* Z C) pinv(Q_row^* C), where R^* Z C is
+         R^* (ZC);
+      3. SVD of M:  Z ~ (Q_col U_M) S_M (Q_row V_M)^*, truncated by ``tol``
+         and ``rmax`` like ``svd_trunc``.
+    Returns (U0, s, V0) like ``svd_trunc``.
+    """
+    ZC = np.asarray(ZC, dtype=np.complex128)
+    ZsR = np.asarray(ZsR, dtype=np.complex128)
+    m, n = ZC.shape[0], ZsR.shape[0]
+    if m == 0 or n == 0:
+        return (np.zeros((m, 0), complex), np.zeros(0), np.zeros((n, 0), complex))
+    qtol = tol * 1e-2
+    r_max = min(int(rmax), ZC.shape[1])
+    Qc, Rc, _ = sla.qr(ZC, mode="economic", pivoting=True)
+    Qc = Qc[:, :max(_pivot_rank(Rc, qtol, min(m, r_max)), 1)]
+    Qr, Rr, _ = sla.qr(ZsR, mode="economic", pivoting=True)
+    Qr = Qr[:, :max(_pivot_rank(Rr, qtol, min(n, r_max)), 1)]
+    RZC = R.conj().T @ ZC
+    M = np.linalg.pinv(R.conj().T @ Qc) @ RZC @ np.linalg.pinv(Qr.conj().T @ C)
     Um, sm, Vmh = np.linalg.svd(M, full_matrices=False)
     r = _rank(sm, tol, rmax)
     return Qc @ Um[:, :r], sm[:r], Qr @ Vmh[:r].conj().T

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmbf.so")
+# MBF_LIB selects another build of the library (e.g. the sanitizer build)
+LIB_PATH = os.environ.get("MBF_LIB") or os.path.join(_HERE, "libmbf.so")
 
 PREC = {"c128": 0, "c64": 1, "bf16x3": 2}
 SPLIT = {"none": 0, "polar": 1, "multiscale": 2}
@@ -66,18 +67,22 @@ class LaunchRecord(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int64), ("rhs", ctypes.c_int64), ("batches", ctypes.c_int64),
-                ("max_concurrent_batches", ctypes.c_int64), ("p50_us", ctypes.c_double),
+                ("max_concurrent_batches", ctypes.c_int64), ("graphs_captured", ctypes.c_int64),
+                ("graph_batches", ctypes.c_int64), ("p50_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double), ("wall_s", ctypes.c_double)]
 
 
 ENTRY_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double))
+MATVEC_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
 EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
            "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
            "mbf_server_submit", "mbf_server_poll", "mbf_server_drain", "mbf_server_stats",
-           "mbf_server_destroy", "mbf_save", "mbf_load", "mbf_autotune", "mbf_apply_scratch", "mbf_scratch_bytes"]
+           "mbf_server_destroy", "mbf_save", "mbf_load", "mbf_autotune", "mbf_apply_scratch", "mbf_scratch_bytes",
+           "mbf_build_matvec"]
 
 
 def lib():
@@ -91,6 +96,8 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
     L.mbf_build.argtypes = [i32, i64, vp, i64, vp, ENTRY_CB, vp, ctypes.POINTER(_Opts), vp, ctypes.POINTER(vp)]
+    L.mbf_build_matvec.argtypes = [i32, i64, vp, i64, vp, MATVEC_CB, vp, ctypes.POINTER(_Opts), vp, vp,
+                                   ctypes.POINTER(vp)]
     L.mbf_import.argtypes = [ctypes.POINTER(_ImportDesc), u32, vp, ctypes.POINTER(vp)]
     L.mbf_multiscale_assemble.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_void_p),
                                           ctypes.POINTER(i64), i64, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
@@ -103,7 +110,7 @@ def lib():
     L.mbf_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.mbf_profile_begin.argtypes = [vp, i32]
     L.mbf_profile_end.argtypes = [vp, ctypes.POINTER(LaunchRecord), i32, ctypes.POINTER(i32)]
-    L.mbf_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.POINTER(vp)]
+    L.mbf_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.c_uint32, ctypes.POINTER(vp)]
     L.mbf_server_submit.argtypes = [vp, vp, i32, i64, vp, i64, vp, i64, vp, ctypes.POINTER(ctypes.c_uint64)]
     L.mbf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     L.mbf_server_drain.argtypes = [vp]
@@ -116,7 +123,7 @@ def lib():
     L.mbf_destroy.argtypes = [vp]
     L.mbf_destroy.restype = None
     L.mbf_last_error.restype = ctypes.c_char_p
-    for name in ("mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
+    for name in ("mbf_build", "mbf_build_matvec", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
                  "mbf_apply_adjoint", "mbf_apply_scratch", "mbf_info", "mbf_profile_begin", "mbf_profile_end",
                  "mbf_server_create", "mbf_server_submit", "mbf_server_poll", "mbf_server_drain",
                  "mbf_server_stats", "mbf_save", "mbf_load", "mbf_autotune"):
@@ -219,6 +226,54 @@ class Factor:
         h = ctypes.c_void_p()
         _check(L.mbf_build(2, x.shape[0], x.ctypes.data, xi.shape[0], xi.ctypes.data, cb, user,
                            ctypes.byref(o), None, ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def build_matvec(cls, x, xi, n, matvec, tol=1e-6, max_rank=20, oversample=10, leaf_side=1, depth=0,
+                     split="polar", center_side=16, seed=0, precs=("c64",), probes=None, threads=0):
+        """mbf_build_matvec (build case (i)): the factorization of a K known
+        only through ``matvec(adjoint, block)``, which returns K @ block
+        (block: nxi x ncols) or K^* @ block (block: nx x ncols) as complex128
+        arrays.  ``probes``: optional (C, R) Gaussian matrices of
+        max_rank + oversample columns (nxi and nx rows); by default the
+        library draws them from ``seed``.  Host FP64 builder."""
+        x = np.ascontiguousarray(x, np.float64)
+        xi = np.ascontiguousarray(xi, np.float64)
+        nx, nxi = x.shape[0], xi.shape[0]
+        L = lib()
+
+        errs = []
+
+        def _mv(_user, adjoint, ncols, src, dst):
+            try:
+                rin, rout = (nx, nxi) if adjoint else (nxi, nx)
+                blk = np.ctypeslib.as_array(src, (2 * rin * ncols,)).view(np.complex128).reshape(ncols, rin).T
+                res = np.asarray(matvec(bool(adjoint), blk), np.complex128)
+                if res.shape != (rout, ncols):
+                    return 2
+                o = np.ctypeslib.as_array(dst, (2 * rout * ncols,))
+                o[:] = np.asfortranarray(res).ravel(order="F").view(np.float64)
+                return 0
+            except Exception as ex:  # any error aborts the build; re-raised below as the cause
+                errs.append(ex)
+                return 1
+
+        cb = MATVEC_CB(_mv)
+        pr = None
+        if probes is not None:
+            C, R = (np.asarray(a, np.complex128) for a in probes)
+            q = max_rank + oversample
+            if C.shape != (nxi, q) or R.shape != (nx, q):
+                raise ValueError("probes must be (nxi x q, nx x q) with q = max_rank + oversample")
+            pr = np.concatenate([np.asfortranarray(C).ravel(order="F"), np.asfortranarray(R).ravel(order="F")])
+        o = _Opts(tol, max_rank, depth, leaf_side, n, SPLIT[split], center_side, oversample, seed,
+                  _mask(precs), threads, BUILDER["host"], 0)
+        h = ctypes.c_void_p()
+        st = L.mbf_build_matvec(2, nx, x.ctypes.data, nxi, xi.ctypes.data, cb, None, ctypes.byref(o),
+                                pr.ctypes.data if pr is not None else None, None, ctypes.byref(h))
+        if st != 0 and errs:
+            raise MBFError(st, lib().mbf_last_error().decode()) from errs[0]
+        _check(st)
         return cls(h)
 
     @classmethod
@@ -347,11 +402,18 @@ def multiscale_assemble(parts, part_idx, nxi, center_idx, center, precs=("c64",)
 
 
 class Server:
-    """Request loop with continuous batching and memory admission (mbf_server_*)."""
+    """Request loop with continuous batching and memory admission (mbf_server_*).
 
-    def __init__(self, mem_budget, nslots=4, max_batch_rhs=256):
+    ``graphs=True`` runs every batch's apply as one launch of a HIP graph
+    captured per (factor, precision, batch width) on fixed per-slot buffers
+    (MBF_SERVER_GRAPHS)."""
+
+    GRAPHS = 1
+
+    def __init__(self, mem_budget, nslots=4, max_batch_rhs=256, graphs=False):
         self._h = ctypes.c_void_p()
-        _check(lib().mbf_server_create(int(mem_budget), nslots, max_batch_rhs, ctypes.byref(self._h)))
+        _check(lib().mbf_server_create(int(mem_budget), nslots, max_batch_rhs, self.GRAPHS if graphs else 0,
+                                       ctypes.byref(self._h)))
         self._live = {}
 
     def submit(self, factor, g, out, prec="c64", ready=True):

@@ -685,11 +685,14 @@ inline int64_t stage_nnz(const DevPart& P, int s) {
   return e - P.w_stage_off[s];
 }
 
-// MBF_BF16_SPLIT_STATE=0 keeps FP32 states between the split-BF16 stages
-// (every stage then splits its input as it stages it through LDS).
-bool split_state_enabled() {
+// States between the split-BF16 stages: MBF_BF16_SPLIT_STATE=0 keeps them
+// FP32 (every stage then splits its input as it stages it through LDS), =1
+// keeps them split whatever the autotuner chose; unset, the autotuner's
+// choice decides (split when it has not timed the factorization).
+int split_state_mode() {
   const char* e = std::getenv("MBF_BF16_SPLIT_STATE");
-  return !(e && e[0] == '0');
+  if (!e || !e[0]) return -1;
+  return e[0] == '0' ? 0 : 1;
 }
 
 template <typename T>
@@ -743,8 +746,9 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
   // Split BF16: the stage kernels pass the state between stages as BF16
   // hi | lo words; the first stage splits the projected FP32 state, the last
   // one writes FP32 for the leaf reconstruction.
-  const bool split = prec == MBF_C64_SPLIT_BF16 && ws_ld < ((int64_t)1 << 23) && split_state_enabled() &&
-                     split_choice(prec, ws_ld, ni) != 0;
+  const int mode = split_state_mode();
+  const bool split = prec == MBF_C64_SPLIT_BF16 && ws_ld < ((int64_t)1 << 23) &&
+                     (mode == 1 || (mode == -1 && split_choice(prec, ws_ld, ni) != 0));
   int s_lo = L, s_hi = -1;  // first and last stage with blocks
   for (int s = 0; s < L; ++s)
     if (P.nblk[s] > 0) {

@@ -202,6 +202,138 @@ Mat merge_rows(const std::vector<const Mat*>& parts, int64_t r0, int64_t r1) {
   return W;
 }
 
+// SVD via random matrix-vector products (Section 2.1, first option) of one
+// middle-level block Z, known only through its products with Gaussian
+// probes: ZC = Z C (m x q) and ZsR = Z^* R (n x q), with C (n x q) and R
+// (m x q), q = rank cap r + oversampling.  Steps, in the paper's order:
+//   (1) orthonormal bases Q_col of ZC and Q_row of Z^* R by pivoted QR, at
+//       most r columns each (the extra probe columns keep the solves of
+//       step 2 overdetermined);
+//   (2) M = pinv(R^* Q_col) (R^* ZC) pinv(Q_row^* C), as two least-squares
+//       solves;
+//   (3) SVD of M:  Z ~ (Q_col U_M) S_M (Q_row V_M)^*, truncated.
+Low matvec_svd(const Mat& ZC, const Mat& ZsR, const Mat& C, const Mat& R, double tol, int64_t rmax) {
+  Low out;
+  const int64_t m = ZC.m, n = ZsR.m;
+  if (m == 0 || n == 0) {
+    out.U0 = Mat(m, 0);
+    out.V0 = Mat(n, 0);
+    return out;
+  }
+  const double qtol = tol * 1e-2;
+  const int64_t r = std::min<int64_t>(rmax, ZC.n);
+  la::QRP qc = la::pivoted_qr(ZC, qtol, r);
+  la::QRP qr = la::pivoted_qr(ZsR, qtol, r);
+  if (qc.k == 0 || qr.k == 0) {  // Z C = 0 or Z^* R = 0: Z = 0 to the probes
+    out.U0 = Mat(m, 0);
+    out.V0 = Mat(n, 0);
+    return out;
+  }
+  const Mat& Qc = qc.Q;  // m x kc
+  const Mat& Qr = qr.Q;  // n x kr
+  // (2) T = pinv(R^* Q_col) (R^* ZC), then M = T pinv(Q_row^* C) via M^* = lstsq((Q_row^* C)^*, T^*)
+  Mat T = la::lstsq(la::matmul_ah(R, Qc), la::matmul_ah(R, ZC));     // kc x q
+  Mat M = la::adjoint(la::lstsq(la::matmul_ah(C, Qr), la::adjoint(T)));  // kc x kr
+  // (3) SVD of M
+  la::SVD d = la::svd(M);
+  const int64_t rk = la::trunc_rank(d.s, tol, rmax);
+  Mat UM(M.m, rk), VM(M.n, rk);
+  for (int64_t j = 0; j < rk; ++j) {
+    for (int64_t i = 0; i < M.m; ++i) UM(i, j) = d.U(i, j);
+    for (int64_t i = 0; i < M.n; ++i) VM(i, j) = d.V(i, j);
+  }
+  out.U0 = la::matmul(Qc, UM);
+  out.V0 = la::matmul(Qr, VM);
+  out.s.assign(d.s.begin(), d.s.begin() + rk);
+  return out;
+}
+
+// Products of case (i) for one part (Section 2.3): K applied to the
+// zero-padded probe C^P_B of every Omega node B at level L - m (rows: all of
+// X, callback order) and K^* applied to R^P_A of every X node A at level m
+// (rows: the part's Omega points, tree point order).  The black box is
+// called on blocks of at most about 1 GiB.
+struct MidProducts {
+  std::vector<Mat> KC;   // per B: nx x q
+  std::vector<Mat> KsR;  // per A: |part Omega points| x q
+};
+
+MidProducts mid_products(const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
+                         const std::vector<int64_t>& os, const MatvecSource& src) {
+  const int L = xt.L, m = L / 2;
+  const int64_t q = src.q, nx = src.nx, nxi = src.nxi;
+  MidProducts P;
+  const int64_t per_call = std::max<int64_t>(1, ((int64_t)1 << 26) / (std::max(nx, nxi) * q));
+  auto call = [&](int adjoint, int64_t ncols, const std::vector<la::cd>& in, std::vector<la::cd>& out) {
+    const int rc = src.mv(src.user, adjoint, ncols, reinterpret_cast<const double*>(in.data()),
+                          reinterpret_cast<double*>(out.data()));
+    if (rc != 0) throw CallbackError("matvec callback returned " + std::to_string(rc));
+  };
+  const int lb = L - m;
+  P.KC.resize(ot.nn(lb));
+  for (int32_t b0 = 0; b0 < ot.nn(lb); b0 += (int32_t)per_call) {
+    const int32_t b1 = (int32_t)std::min<int64_t>(ot.nn(lb), b0 + per_call);
+    const int64_t nc = (int64_t)(b1 - b0) * q;
+    std::vector<la::cd> in((size_t)(nxi * nc)), out((size_t)(nx * nc));
+    for (int32_t b = b0; b < b1; ++b)
+      for (int64_t p = ot.off[lb][b]; p < ot.off[lb][b + 1]; ++p) {
+        const int64_t g = os[ot.perm[p]];
+        for (int64_t c = 0; c < q; ++c) in[(size_t)(g + ((b - b0) * q + c) * nxi)] = src.C[(size_t)(g + c * nxi)];
+      }
+    call(0, nc, in, out);
+    for (int32_t b = b0; b < b1; ++b) {
+      Mat Y(nx, q);
+      std::copy(out.begin() + (size_t)((b - b0) * q * nx), out.begin() + (size_t)((b - b0 + 1) * q * nx), Y.a.begin());
+      P.KC[b] = std::move(Y);
+    }
+  }
+  const int64_t npart = (int64_t)os.size();
+  P.KsR.resize(xt.nn(m));
+  for (int32_t a0 = 0; a0 < xt.nn(m); a0 += (int32_t)per_call) {
+    const int32_t a1 = (int32_t)std::min<int64_t>(xt.nn(m), a0 + per_call);
+    const int64_t nc = (int64_t)(a1 - a0) * q;
+    std::vector<la::cd> in((size_t)(nx * nc)), out((size_t)(nxi * nc));
+    for (int32_t a = a0; a < a1; ++a)
+      for (int64_t p = xt.off[m][a]; p < xt.off[m][a + 1]; ++p) {
+        const int64_t g = xs[xt.perm[p]];
+        for (int64_t c = 0; c < q; ++c) in[(size_t)(g + ((a - a0) * q + c) * nx)] = src.R[(size_t)(g + c * nx)];
+      }
+    call(1, nc, in, out);
+    for (int32_t a = a0; a < a1; ++a) {
+      Mat W(npart, q);
+      for (int64_t c = 0; c < q; ++c)
+        for (int64_t j = 0; j < npart; ++j) W(j, c) = out[(size_t)(os[j] + ((a - a0) * q + c) * nxi)];
+      P.KsR[a] = std::move(W);
+    }
+  }
+  return P;
+}
+
+// Middle-level factorization of pair (ia, ib) from the products of case (i).
+Low matvec_pair(const MidProducts& P, const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
+                const std::vector<int64_t>& os, const MatvecSource& src, int32_t ia, int32_t ib, const mbf_opts& o) {
+  ScopedUs timer(g_mid_us);
+  const int L = xt.L, m = L / 2;
+  const int64_t q = src.q;
+  const int64_t ma = xt.size(m, ia), nb = ot.size(L - m, ib);
+  Mat ZC(ma, q), Ra(ma, q), ZsR(nb, q), Cb(nb, q);
+  for (int64_t i = 0; i < ma; ++i) {
+    const int64_t g = xs[xt.perm[xt.off[m][ia] + i]];
+    for (int64_t c = 0; c < q; ++c) {
+      ZC(i, c) = P.KC[ib](g, c);
+      Ra(i, c) = src.R[(size_t)(g + c * src.nx)];
+    }
+  }
+  for (int64_t j = 0; j < nb; ++j) {
+    const int64_t t = ot.perm[ot.off[L - m][ib] + j];
+    for (int64_t c = 0; c < q; ++c) {
+      ZsR(j, c) = P.KsR[ia](t, c);
+      Cb(j, c) = src.C[(size_t)(os[t] + c * src.nxi)];
+    }
+  }
+  return matvec_svd(ZC, ZsR, Cb, Ra, o.tol, o.max_rank);
+}
+
 // Progress lines on stderr when MBF_VERBOSE is set (long builds).
 struct Progress {
   const char* what;
@@ -289,8 +421,13 @@ static int default_threads() {
   return (int)std::max(1u, std::thread::hardware_concurrency());
 }
 
-HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
-                      const std::vector<int64_t>& os, mbf_entry_cb cb, void* user, const mbf_opts& o) {
+namespace {
+// The build of Section 2 on given trees; the middle level comes from the
+// entry callback (case (ii)) or, with `src`, from products with the black
+// box (case (i)).
+HostFactor build_host_impl(const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
+                           const std::vector<int64_t>& os, mbf_entry_cb cb, void* user, const mbf_opts& o,
+                           const MatvecSource* src) {
   HostFactor f;
   const int L = xt.L;
   const int m = L / 2;
@@ -322,9 +459,13 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
     return std::make_pair(a, b);
   };
 
-  // Sample size of the middle level from one probe pair.
+  // Case (i): every product with the black box up front.  Case (ii): the
+  // sample size of the middle level from one probe pair.
+  MidProducts mp;
   int64_t q0 = 32;
-  {
+  if (src) {
+    mp = mid_products(xt, ot, xs, os, *src);
+  } else {
     int64_t r = 0;
     (void)middle_pair(c, xt, ot, m, 0, 0, o, 32, &r);
     q0 = std::max<int64_t>(32, r + 2 * o.oversample);
@@ -336,7 +477,8 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   parallel_for(xt.nn(m), threads, [&](int64_t ia_m) {
     std::map<std::pair<int32_t, int32_t>, Mat> U;  // (ia, ib) at current stage
     for (int32_t ib = 0; ib < ot.nn(L - m); ++ib) {
-      Low lw = middle_pair(c, xt, ot, m, (int32_t)ia_m, ib, o, q0);
+      Low lw = src ? matvec_pair(mp, xt, ot, xs, os, *src, (int32_t)ia_m, ib, o)
+                   : middle_pair(c, xt, ot, m, (int32_t)ia_m, ib, o, q0);
       pm.tick();
       const int64_t r = (int64_t)lw.s.size();
       Mat Uf = lw.U0;
@@ -483,6 +625,12 @@ HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>
   }
   return f;
 }
+}  // namespace
+
+HostFactor build_host(const Tree& xt, const Tree& ot, const std::vector<int64_t>& xs,
+                      const std::vector<int64_t>& os, mbf_entry_cb cb, void* user, const mbf_opts& o) {
+  return build_host_impl(xt, ot, xs, os, cb, user, o, nullptr);
+}
 
 namespace {
 
@@ -540,9 +688,10 @@ Error finish_device_part(const Tree& xt, const Tree& ot, const std::vector<int64
 }  // namespace
 
 Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, mbf_entry_cb cb, void* user,
-                   const mbf_opts& o, DevFactor& F) {
+                   const mbf_opts& o, DevFactor& F, const MatvecSource* src) {
   const int64_t n = o.grid_n;
   if (nx != n * n || nxi != n * n) return {MBF_ERR_INVALID_ARG, "points must form n x n grids (grid_n)"};
+  if (src && o.builder != MBF_BUILD_HOST) return {MBF_ERR_UNSUPPORTED, "the matvec build runs on the host builder"};
   // Device builder: the entries are evaluated on the GPU, so the kernel must
   // be one the device knows (the ready-made callbacks).
   const bool dev = o.builder == MBF_BUILD_DEVICE;
@@ -599,7 +748,7 @@ Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, m
     Tree xt = tree_from_leaf_codes(L, nx, xc.data());
     Tree ot = tree_from_leaf_codes(L, nxi, oc.data());
     if (dev) return finish_device_part(xt, ot, xs, os, DK, o, F);
-    HostFactor f = build_host(xt, ot, xs, os, cb, user, o);
+    HostFactor f = build_host_impl(xt, ot, xs, os, cb, user, o, src);
     return finish_part(f, nullptr, F.prec_mask, F);
   }
   // Multiscale (Section 4.1 corona split, half-open reading):
@@ -632,7 +781,7 @@ Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, m
       if (e.st != MBF_OK) return e;
       continue;
     }
-    HostFactor f = build_host(xt, ot, xs, idx, cb, user, o);
+    HostFactor f = build_host_impl(xt, ot, xs, idx, cb, user, o, src);
     Error e = finish_part(f, idx.data(), F.prec_mask, F);
     if (e.st != MBF_OK) return e;
   }
@@ -649,10 +798,18 @@ Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, m
   } else if (!cen_idx.empty()) {
     std::vector<int64_t> rows(nx);
     std::iota(rows.begin(), rows.end(), 0);
-    std::vector<cd> KC((size_t)(nx * (int64_t)cen_idx.size()));
-    const int rc = cb(user, nx, rows.data(), (int64_t)cen_idx.size(), cen_idx.data(),
-                      reinterpret_cast<double*>(KC.data()));
-    if (rc != 0) throw CallbackError("entry callback returned " + std::to_string(rc));
+    const int64_t nc = (int64_t)cen_idx.size();
+    std::vector<cd> KC((size_t)(nx * nc));
+    int rc;
+    if (src) {  // case (i): K applied to the unit vectors of the center
+      std::vector<cd> E((size_t)(nxi * nc));
+      for (int64_t j = 0; j < nc; ++j) E[(size_t)(cen_idx[j] + j * nxi)] = cd(1, 0);
+      rc = src->mv(src->user, 0, nc, reinterpret_cast<const double*>(E.data()), reinterpret_cast<double*>(KC.data()));
+      if (rc != 0) throw CallbackError("matvec callback returned " + std::to_string(rc));
+    } else {
+      rc = cb(user, nx, rows.data(), nc, cen_idx.data(), reinterpret_cast<double*>(KC.data()));
+      if (rc != 0) throw CallbackError("entry callback returned " + std::to_string(rc));
+    }
     Error e = upload_center(F, KC, cen_idx, F.prec_mask);
     if (e.st != MBF_OK) return e;
     F.nnz += (int64_t)KC.size();

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <exception>
 #include <new>
+#include <random>
 #include <string>
 
 #include "builder.h"
@@ -122,6 +123,23 @@ mbf_status mbf_import(const mbf_import_desc* d, uint32_t prec_mask, void* stream
   });
 }
 
+// Owns a factor under construction: released (device memory included) when
+// the build fails or throws before the handle is given out.
+struct FactorGuard {
+  mbf_factor_s* h = new mbf_factor_s();
+  ~FactorGuard() {
+    if (h) {
+      free_factor(h->dev);
+      delete h;
+    }
+  }
+  mbf_factor_s* release() {
+    mbf_factor_s* p = h;
+    h = nullptr;
+    return p;
+  }
+};
+
 mbf_status mbf_build(int32_t dim, int64_t nx, const double* x, int64_t nxi, const double* xi,
                      mbf_entry_cb cb, void* user, const mbf_opts* opts, void* stream, mbf_factor* out) {
   (void)stream;
@@ -132,14 +150,46 @@ mbf_status mbf_build(int32_t dim, int64_t nx, const double* x, int64_t nxi, cons
     if (!x || !xi || !cb || !opts || nx <= 0 || nxi <= 0) return fail(MBF_ERR_INVALID_ARG, "null or empty input");
     std::string why;
     if (!validate_opts(*opts, why)) return fail(MBF_ERR_INVALID_ARG, why);
-    auto* h = new mbf_factor_s();
-    Error e = build_factor(nx, x, nxi, xi, cb, user, *opts, h->dev);
-    if (e.st != MBF_OK) {
-      free_factor(h->dev);
-      delete h;
-      return from(e);
+    FactorGuard g;
+    Error e = build_factor(nx, x, nxi, xi, cb, user, *opts, g.h->dev);
+    if (e.st != MBF_OK) return from(e);
+    *out = g.release();
+    return MBF_OK;
+  });
+}
+
+mbf_status mbf_build_matvec(int32_t dim, int64_t nx, const double* x, int64_t nxi, const double* xi,
+                            mbf_matvec_cb mv, void* user, const mbf_opts* opts, const double* probes,
+                            void* stream, mbf_factor* out) {
+  (void)stream;
+  return guarded([&]() -> mbf_status {
+    if (!out) return fail(MBF_ERR_INVALID_ARG, "null output handle");
+    *out = nullptr;
+    if (dim != 2) return fail(MBF_ERR_UNSUPPORTED, "only dim = 2 is supported");
+    if (!x || !xi || !mv || !opts || nx <= 0 || nxi <= 0) return fail(MBF_ERR_INVALID_ARG, "null or empty input");
+    std::string why;
+    if (!validate_opts(*opts, why)) return fail(MBF_ERR_INVALID_ARG, why);
+    if (opts->oversample < 1) return fail(MBF_ERR_INVALID_ARG, "the matvec build needs oversample >= 1");
+    if (opts->builder != MBF_BUILD_HOST) return fail(MBF_ERR_UNSUPPORTED, "the matvec build runs on the host builder");
+    const int64_t q = (int64_t)opts->max_rank + opts->oversample;
+    std::vector<cd> C, R;
+    if (probes) {
+      const cd* p = reinterpret_cast<const cd*>(probes);
+      C.assign(p, p + nxi * q);
+      R.assign(p + nxi * q, p + (nxi + nx) * q);
+    } else {  // complex Gaussian entries, E|z|^2 = 1
+      std::mt19937_64 rng(opts->seed ^ 0x5eed0f9a11ull);
+      std::normal_distribution<double> nd(0.0, std::sqrt(0.5));
+      C.resize((size_t)(nxi * q));
+      R.resize((size_t)(nx * q));
+      for (auto& z : C) z = cd(nd(rng), nd(rng));
+      for (auto& z : R) z = cd(nd(rng), nd(rng));
     }
-    *out = h;
+    MatvecSource src{mv, user, C.data(), R.data(), q, nx, nxi};
+    FactorGuard g;
+    Error e = build_factor(nx, x, nxi, xi, nullptr, nullptr, *opts, g.h->dev, &src);
+    if (e.st != MBF_OK) return from(e);
+    *out = g.release();
     return MBF_OK;
   });
 }

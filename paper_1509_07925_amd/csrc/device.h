@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <cstdint>
 #include <vector>
 
@@ -126,7 +128,14 @@ size_t scratch_bytes();
 
 }  // namespace mbf
 
+namespace mbf {
+// Process-wide serial numbers of factor handles (never reused, unlike
+// addresses): the server keys its captured graphs by them.
+inline std::atomic<uint64_t> g_factor_serial{1};
+}  // namespace mbf
+
 // The opaque handle of the C ABI.
 struct mbf_factor_s {
   mbf::DevFactor dev;
+  uint64_t serial = mbf::g_factor_serial.fetch_add(1);
 };

@@ -15,6 +15,18 @@
 // by polling the events; a request's latency is completion - submission on
 // the host clock.
 //
+// Graph mode (MBF_SERVER_GRAPHS): each slot keeps one fixed region of the
+// pool for its staging blocks and workspace, sized for the largest batch it
+// has run (grown when a larger one comes, which drops the slot's graphs; the
+// regions of idle slots are given back when the pool cannot otherwise hold a
+// growth).  The apply's launches for a (factor, precision, batch width) are
+// captured once on the slot's stream into a HIP graph and replayed for every
+// later batch of that kind; batch widths are rounded up to a power of two of
+// at least 16 columns (within max_batch_rhs) so that few graphs serve every
+// mix, the padding columns computing results nobody reads (the apply treats
+// every column on its own).  Per batch the slot issues the gather copies, one
+// graph launch and the scatter copies.
+//
 // Admission never fails a request that fits alone: when a batch of several
 // requests exceeds the pool, trailing requests are left in the queue until
 // the batch fits; only a request whose own staging and workspace exceed the
@@ -35,6 +47,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "device.h"
@@ -110,14 +123,33 @@ struct Pool {
   }
 };
 
+using GraphKey = std::tuple<uint64_t, int, int64_t>;  // factor serial, precision, batch width
+
+constexpr size_t kMaxGraphsPerSlot = 256;
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
   mbf_status st = MBF_OK;  // status given to every request of the batch
   std::vector<Request> reqs;
-  size_t off = 0, bytes = 0;
+  size_t off = 0, bytes = 0;  // the batch's reservation (direct launches)
+  // graph mode: the slot's fixed region and its captured applies
+  size_t fix_off = SIZE_MAX, fix_bytes = 0;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
 };
+
+// Smallest power of two >= max(cols, 16), kept within max(max_rhs, cols).
+int64_t batch_width(int64_t cols, int64_t max_rhs) {
+  int64_t w = 16;
+  while (w < cols) w *= 2;
+  return std::max(cols, std::min(w, max_rhs));
+}
 
 }  // namespace
 
@@ -126,6 +158,7 @@ struct Server {
   Pool pool;
   std::vector<Slot> slots;
   int64_t max_batch_rhs = 256;
+  bool use_graphs = false;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request> queue;
@@ -136,7 +169,8 @@ struct Server {
   std::atomic<uint64_t> next_id{1};
   bool stop = false;
   std::string error;
-  int64_t batches = 0, rhs_done = 0, requests_done = 0, max_concurrent = 0;
+  int64_t batches = 0, rhs_done = 0, requests_done = 0, max_concurrent = 0, graphs_captured = 0,
+          graph_batches = 0;
   clk::time_point t_first{}, t_last{};
   std::thread th;
 
@@ -181,24 +215,52 @@ struct Server {
       cols -= queue[take.back()].nrhs;
       take.pop_back();
     }
-    const size_t need = batch_bytes(head, cols);
-    if (need > pool.size) {
+    if (batch_bytes(head, cols) > pool.size) {
       // the head request alone can never fit: it fails, the rest proceed
       error = "request larger than the server memory budget";
       complete(head, MBF_ERR_OOM, clk::now());
       queue.pop_front();
       return true;
     }
-    const size_t off = pool.alloc(need);
-    if (off == SIZE_MAX) return false;  // admission: wait for memory
+    // columns of the apply: the batch's own, or its graph width
+    int64_t width = cols;
+    if (use_graphs) {
+      width = batch_width(cols, max_batch_rhs);
+      if (batch_bytes(head, width) > pool.size) width = cols;
+    }
+    const size_t need = batch_bytes(head, width);
+    size_t off;
+    if (use_graphs) {
+      if (s.fix_bytes < need) {
+        // grow to the factorization's widest batch when every slot could hold
+        // one that size, so that the region (and its graphs) stays put
+        const size_t full = batch_bytes(head, batch_width(max_batch_rhs, max_batch_rhs));
+        const bool roomy = full > need && full <= pool.size / slots.size();
+        if (!(roomy && grow_region(s, full)) && !grow_region(s, need)) return false;  // admission: wait
+      }
+      off = s.fix_off;
+    } else {
+      off = pool.alloc(need);
+      if (off == SIZE_MAX) return false;  // admission: wait for memory
+    }
     const DevFactor& F = head.f->dev;
     const size_t es = head.prec == MBF_C128 ? 16 : 8;
     char* gb = pool.base + off;
-    char* ub = gb + (size_t)F.nxi * cols * es;
-    const size_t io = (size_t)(F.nxi + F.nx) * (size_t)cols * es;
+    char* ub = gb + (size_t)F.nxi * width * es;
+    const size_t io = (size_t)(F.nxi + F.nx) * (size_t)width * es;
     char* ws = pool.base + off + (io + 255) / 256 * 256;
+    const size_t ws_bytes = need - (size_t)(ws - gb);
     s.reqs.clear();
     s.st = MBF_OK;
+    hipGraphExec_t exec = nullptr;
+    if (use_graphs) {
+      // capture before this batch's copies are on the (idle) stream
+      Error e = slot_graph(s, head, width, gb, ub, ws, ws_bytes, &exec);
+      if (e.st != MBF_OK) {
+        error = e.msg;
+        s.st = e.st;
+      }
+    }
     int64_t c0 = 0;
     for (size_t k = 0; k < take.size(); ++k) {
       const Request& r = queue[take[k]];
@@ -209,10 +271,20 @@ struct Server {
       c0 += r.nrhs;
       s.reqs.push_back(r);
     }
-    Error e = launch_apply(F, head.prec, false, cols, gb, F.nxi, ub, F.nx, ws, need - (ws - gb), s.stream);
-    if (e.st != MBF_OK) {
-      error = e.msg;
-      s.st = e.st;
+    if (s.st == MBF_OK) {
+      if (exec) {
+        if (hipGraphLaunch(exec, s.stream) != hipSuccess) {
+          error = "graph launch failed";
+          s.st = MBF_ERR_HIP;
+        }
+        ++graph_batches;
+      } else {
+        Error e = launch_apply(F, head.prec, false, cols, gb, F.nxi, ub, F.nx, ws, ws_bytes, s.stream);
+        if (e.st != MBF_OK) {
+          error = e.msg;
+          s.st = e.st;
+        }
+      }
     }
     if (s.st == MBF_OK) {
       c0 = 0;
@@ -228,9 +300,62 @@ struct Server {
     for (size_t k = take.size(); k-- > 0;) queue.erase(queue.begin() + (std::ptrdiff_t)take[k]);
     s.busy = true;
     s.off = off;
-    s.bytes = need;
+    s.bytes = use_graphs ? 0 : need;
     ++batches;
     return true;
+  }
+
+  // Graph mode: give slot s a fixed region of at least `need` bytes (its
+  // graphs point into the old one and are dropped).  When the pool cannot
+  // hold it, the regions of idle slots are released too; false when even
+  // then it does not fit (the batch waits).
+  bool grow_region(Slot& s, size_t need) {
+    auto release = [&](Slot& t) {
+      t.drop_graphs();
+      if (t.fix_off != SIZE_MAX) pool.release(t.fix_off, t.fix_bytes);
+      t.fix_off = SIZE_MAX;
+      t.fix_bytes = 0;
+    };
+    release(s);
+    size_t off = pool.alloc(need);
+    if (off == SIZE_MAX) {
+      for (auto& t : slots)
+        if (&t != &s && !t.busy) release(t);
+      off = pool.alloc(need);
+    }
+    if (off == SIZE_MAX) return false;
+    s.fix_off = off;
+    s.fix_bytes = need;
+    return true;
+  }
+
+  // Graph mode: the captured apply of `width` columns of the head request's
+  // factorization from the slot's staging g block into its u block.
+  Error slot_graph(Slot& s, const Request& head, int64_t width, char* gb, char* ub, char* ws, size_t ws_bytes,
+                   hipGraphExec_t* exec) {
+    const GraphKey key{head.f->serial, head.prec, width};
+    auto it = s.graphs.find(key);
+    if (it != s.graphs.end()) {
+      *exec = it->second;
+      return {MBF_OK, ""};
+    }
+    if (s.graphs.size() >= kMaxGraphsPerSlot) s.drop_graphs();
+    const DevFactor& F = head.f->dev;
+    if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return {MBF_ERR_HIP, "hipStreamBeginCapture failed"};
+    Error e = launch_apply(F, head.prec, false, width, gb, F.nxi, ub, F.nx, ws, ws_bytes, s.stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s.stream, &g);
+    if (e.st == MBF_OK && ec != hipSuccess) e = {MBF_ERR_HIP, "hipStreamEndCapture failed"};
+    hipGraphExec_t x = nullptr;
+    if (e.st == MBF_OK && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess)
+      e = {MBF_ERR_HIP, "hipGraphInstantiate failed"};
+    if (g) (void)hipGraphDestroy(g);
+    if (e.st != MBF_OK) return e;
+    s.graphs[key] = x;
+    ++graphs_captured;
+    *exec = x;
+    return {MBF_OK, ""};
   }
 
   void loop() {
@@ -250,7 +375,7 @@ struct Server {
           }
           for (const Request& r : s.reqs) complete(r, s.st, now);
           t_last = now;
-          pool.release(s.off, s.bytes);
+          if (s.bytes) pool.release(s.off, s.bytes);
           s.busy = false;
           s.reqs.clear();
         } else {
@@ -284,8 +409,9 @@ struct mbf_server_s : Server {};
 
 extern "C" {
 
-mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, mbf_server* out) {
-  if (!out || mem_budget == 0 || nslots <= 0 || nslots > 64 || max_batch_rhs <= 0) {
+mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batch_rhs, uint32_t flags,
+                             mbf_server* out) {
+  if (!out || mem_budget == 0 || nslots <= 0 || nslots > 64 || max_batch_rhs <= 0 || (flags & ~MBF_SERVER_GRAPHS)) {
     mbf::set_error("invalid server arguments");
     return MBF_ERR_INVALID_ARG;
   }
@@ -298,6 +424,7 @@ mbf_status mbf_server_create(size_t mem_budget, int32_t nslots, int64_t max_batc
     return MBF_ERR_OOM;
   }
   s->max_batch_rhs = max_batch_rhs;
+  s->use_graphs = (flags & MBF_SERVER_GRAPHS) != 0;
   s->slots.resize(nslots);
   for (auto& sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -407,6 +534,8 @@ mbf_status mbf_server_stats(mbf_server srv, mbf_server_stats_t* out) {
   out->rhs = s->rhs_done;
   out->batches = s->batches;
   out->max_concurrent_batches = s->max_concurrent;
+  out->graphs_captured = s->graphs_captured;
+  out->graph_batches = s->graph_batches;
   out->p50_us = pct(0.50);
   out->p99_us = pct(0.99);
   out->mean_us = v.empty() ? 0.0 : [&]() { double t = 0; for (double x : v) t += x; return t / v.size(); }();
@@ -425,6 +554,7 @@ void mbf_server_destroy(mbf_server srv) {
   if (s->th.joinable()) s->th.join();
   for (auto& sl : s->slots) {
     (void)hipStreamSynchronize(sl.stream);
+    sl.drop_graphs();
     (void)hipStreamDestroy(sl.stream);
     (void)hipEventDestroy(sl.done);
   }

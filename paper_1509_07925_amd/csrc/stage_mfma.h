@@ -23,9 +23,10 @@ inline int num_variants(int prec, bool in_split = false) {
 // force_variant >= 0 bypasses the tuned choice.  in_split / out_split (split
 // BF16 precision only): the input / output state is split, i.e. each complex
 // entry is held as the BF16 words hi = Re_hi | Im_hi << 16 and
-// lo = Re_lo | Im_lo << 16, in two planes per column (hi words at 2 ld n + row,
-// lo words at 2 ld n + ld + row, for the FP32 column stride ld); interior
-// stages pass the state on in that form.  in_split needs ld_in < 2^23.
+// lo = Re_lo | Im_lo << 16, side by side in the 8 bytes of the entry (hi at
+// 32-bit word 2 (ld n + row), lo at the next word, for the column stride ld);
+// interior stages pass the state on in that form.  in_split needs
+// ld_in < 2^23.
 Error launch_stage_mfma(const DevPart& P, int s, int prec, bool adjoint, const BlockDesc* blk,
                         const void* W, const void* in, int64_t ld_in, void* out, int64_t ld_out,
                         int nrhs, const float* scale, hipStream_t st, bool in_split = false,

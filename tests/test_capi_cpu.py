@@ -236,3 +236,67 @@ def test_column_bar_catches_one_bad_column():
     got[3, 5] += 1e-3 * np.abs(ref[:, 5]).max()  # one wrong entry
     with pytest.raises(AssertionError):
         assert_columns_close(got, ref, 1e-6)
+
+
+def test_matvec_build_rejects_bad_options_and_reports_callback_errors():
+    """mbf_build_matvec: oversample 0 and the device builder are refused
+    before the black box is called; a black box that fails aborts the build
+    with MBF_ERR_CALLBACK and leaves the handle null."""
+    lib = mbf.lib()
+    n = 8
+    x = np.ascontiguousarray(W.grid_x_integer(n))
+    xi = np.ascontiguousarray(W.grid_omega(n))
+    calls = []
+    cb = mbf.MATVEC_CB(lambda user, adj, ncols, src, dst: calls.append(adj) or 5)
+    h = ctypes.c_void_p(12345)
+    o = mbf._Opts(1e-6, 8, 0, 1, n, 0, 16, 0, 0, 2, 1, 0, 0)  # oversample 0
+    assert lib.mbf_build_matvec(2, n * n, x.ctypes.data, n * n, xi.ctypes.data, cb, None, ctypes.byref(o), None,
+                                None, ctypes.byref(h)) == -1
+    assert not h.value
+    o = mbf._Opts(1e-6, 8, 0, 1, n, 0, 16, 4, 0, 2, 1, 1, 0)  # device builder
+    assert lib.mbf_build_matvec(2, n * n, x.ctypes.data, n * n, xi.ctypes.data, cb, None, ctypes.byref(o), None,
+                                None, ctypes.byref(h)) == -5
+    assert not calls
+    o = mbf._Opts(1e-6, 8, 0, 1, n, 0, 16, 4, 0, 2, 1, 0, 0)
+    h = ctypes.c_void_p(12345)
+    assert lib.mbf_build_matvec(2, n * n, x.ctypes.data, n * n, xi.ctypes.data, cb, None, ctypes.byref(o), None,
+                                None, ctypes.byref(h)) == -3
+    assert calls == [0] and not h.value
+    assert "matvec callback" in lib.mbf_last_error().decode()
+
+
+def test_matvec_build_probes_are_zero_padded_gaussians():
+    """The library's case (i) products (Section 2.3): one block of q columns
+    per middle-level Omega node B holding the given C on the points of B and
+    zeros elsewhere (the B cover Omega once), one per middle-level X node A
+    holding R likewise.  The host factorization then runs to the end (on a
+    machine without a GPU the upload of the factors fails)."""
+    n, rmax, os_ = 8, 6, 4
+    x, xi = W.grid_x_integer(n), W.grid_omega(n)
+    N, q = n * n, rmax + os_
+    D = kernels.dft(n)(x, xi)
+    rng = np.random.default_rng(0)
+    C = rng.standard_normal((N, q)) + 1j * rng.standard_normal((N, q))
+    R = rng.standard_normal((N, q)) + 1j * rng.standard_normal((N, q))
+    seen = {0: [], 1: []}
+
+    def mv(adj, blk):
+        seen[int(adj)].append(np.array(blk))
+        return D.conj().T @ blk if adj else D @ blk
+
+    try:
+        mbf.Factor.build_matvec(x, xi, n, mv, tol=1e-10, max_rank=rmax, oversample=os_, leaf_side=1, split="none",
+                                probes=(C, R), precs=["c128"])
+    except mbf.MBFError as e:
+        assert e.status in (-2, -4), e
+    for adj, P, npts in ((0, C, 4), (1, R, 16)):  # L = 3: Omega level 2 (4 points), X level 1 (16 points)
+        blk = np.hstack(seen[adj])
+        assert blk.shape[1] % q == 0
+        covered = np.zeros(N, int)
+        for b in range(blk.shape[1] // q):
+            part = blk[:, b * q:(b + 1) * q]
+            rows = np.flatnonzero(np.abs(part).sum(axis=1))
+            assert rows.size == npts
+            np.testing.assert_array_equal(part[rows], P[rows])
+            covered[rows] += 1
+        assert np.all(covered == 1)

@@ -43,32 +43,49 @@ def _np(t):
     return t.t().contiguous().cpu().numpy().astype(np.complex128).T
 
 
-def test_mixed_stream_equals_solo_and_oracle():
+def _hold_stream(dev):
+    """Queue tens of milliseconds of work on the current stream: requests
+    submitted next (each waits for an event recorded after it) pile up in
+    the server's queue while the first ones hold the slots, so the later
+    ones share batches whatever the host's timing."""
+    busy = torch.randn((4096, 4096), device=dev)
+    for _ in range(6):
+        busy = busy @ busy
+        busy = busy / busy.abs().max()
+    return busy
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_mixed_stream_equals_solo_and_oracle(graphs):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1509_07925_amd as mbf
     dev = torch.device("cuda:0")
     facs = _factors()
     rng = np.random.default_rng(0)
-    srv = mbf.Server(mem_budget=256 << 20, nslots=4, max_batch_rhs=128)
-    reqs = []
+    srv = mbf.Server(mem_budget=256 << 20, nslots=4, max_batch_rhs=128, graphs=graphs)
+    pending = []
     for i in range(60):
         k = int(rng.integers(len(facs)))
-        F, bf, N = facs[k]
+        N = facs[k][2]
         nr = int(rng.integers(1, 33))
         g = W.rhs(N, nr, seed=100 + i)
-        gt = _col(g, dev)
-        ut = torch.empty((nr, N), dtype=torch.complex64, device=dev).t()
-        torch.cuda.synchronize()
-        rid = srv.submit(F, gt, ut)
-        reqs.append((rid, k, g, gt, ut))
-        if i % 7 == 0:
-            time.sleep(0.002)  # arrivals while earlier batches run
+        pending.append((k, g, _col(g, dev), torch.empty((nr, N), dtype=torch.complex64, device=dev).t()))
+    reqs = []
+    for i, (k, g, gt, ut) in enumerate(pending):
+        if i % 20 == 0:
+            _hold_stream(dev)  # three waves of arrivals while earlier batches wait or run
+        reqs.append((srv.submit(facs[k][0], gt, ut), k, g, gt, ut))
     srv.drain()
     st = srv.stats()
     assert st["requests"] == 60
     assert st["batches"] < 60  # requests were co-batched
     assert st["p99_us"] >= st["p50_us"] > 0
+    if graphs:  # every batch replayed a graph; at most one capture per (slot, factor, width)
+        assert st["graph_batches"] == st["batches"]
+        assert 1 <= st["graphs_captured"] <= min(st["batches"], 4 * len(facs) * 4)
+    else:
+        assert st["graph_batches"] == 0 and st["graphs_captured"] == 0
     for rid, k, g, gt, ut in reqs:
         done, lat = srv.poll(rid)
         assert done and lat > 0
@@ -175,4 +192,77 @@ def test_request_waits_for_its_input_event():
     done, _ = srv.poll(rid)
     assert done
     assert_columns_close(_np(ut), bf.apply(g), 1e-6, "request after a slow producer")
+    srv.close()
+
+
+def test_graph_regions_are_given_back_between_factorizations():
+    """Graph mode with a pool that holds one slot region at a time:
+    alternating factorizations make a slot give back its region and take a
+    larger one (dropping its graphs), and every result stays right."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_07925_amd as mbf
+    dev = torch.device("cuda:0")
+    facs = _factors()
+    big = max(2 * N * 16 * 8 + F.workspace_size("c64", 16) for F, _, N in facs)
+    srv = mbf.Server(mem_budget=big + 8192, nslots=2, max_batch_rhs=16, graphs=True)
+    for rnd in range(3):
+        for k in (0, 1, 0):
+            F, bf, N = facs[k]
+            g = W.rhs(N, 5, seed=400 + 10 * rnd + k)
+            gt = _col(g, dev)
+            ut = torch.empty((5, N), dtype=torch.complex64, device=dev).t()
+            torch.cuda.synchronize()
+            rid = srv.submit(F, gt, ut)
+            srv.drain()
+            done, _ = srv.poll(rid)
+            assert done
+            assert_columns_close(_np(ut), bf.apply(g), 1e-6, "round %d factor %d" % (rnd, k))
+    st = srv.stats()
+    assert st["graph_batches"] == 9 and st["graphs_captured"] >= 3
+    srv.close()
+
+
+def test_device_built_mix_at_n64_and_n128():
+    """Served mix over device-built factorizations of the 2D DFT and the
+    multiscale FIO at n = 64 and 128, with graph launches: every request's
+    result equals the same request applied alone (per column), and on 64
+    sampled rows matches the direct sum within the factorization's bar."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_07925_amd as mbf
+    dev = torch.device("cuda:0")
+    facs = []
+    for kern, n, tol, split in (("dft", 64, 1e-6, "none"), ("fio", 64, 1e-4, "multiscale"),
+                                ("dft", 128, 1e-6, "none"), ("fio", 128, 1e-4, "multiscale")):
+        x, xi = (W.grid_x_integer(n), W.grid_omega(n)) if kern == "dft" else (W.grid_x_unit(n), W.grid_omega(n))
+        F = mbf.Factor.build(x, xi, n, kernel=kern, tol=tol, leaf_side=4, split=split, precs=["c64"],
+                             builder="device")
+        K = kernels.dft(n) if kern == "dft" else kernels.fio_radon(n)
+        facs.append((F, K, x, xi, n * n, tol))
+    rng = np.random.default_rng(5)
+    srv = mbf.Server(mem_budget=1 << 30, nslots=4, max_batch_rhs=128, graphs=True)
+    pending = []
+    for i in range(48):
+        k = int(rng.integers(len(facs)))
+        N = facs[k][4]
+        nr = int(rng.integers(1, 33))
+        g = W.rhs(N, nr, seed=500 + i)
+        pending.append((k, g, _col(g, dev), torch.empty((nr, N), dtype=torch.complex64, device=dev).t()))
+    reqs = []
+    for i, (k, g, gt, ut) in enumerate(pending):
+        if i % 16 == 0:
+            _hold_stream(dev)  # three waves of arrivals while earlier batches wait or run
+        reqs.append((srv.submit(facs[k][0], gt, ut), k, g, gt, ut))
+    srv.drain()
+    st = srv.stats()
+    assert st["requests"] == 48 and st["graph_batches"] == st["batches"] < 48
+    for rid, k, g, gt, ut in reqs:
+        F, K, x, xi, N, tol = facs[k]
+        mixed = _np(ut)
+        assert_columns_close(mixed, _np(F.apply(gt)), 1e-6, "request %d: mix vs alone" % rid)
+        rows = W.sample_rows(N, 64, seed=rid)
+        ref = direct.direct_rows(K, x, xi, g, rows, block=64)
+        err = np.linalg.norm(mixed[rows] - ref) / np.linalg.norm(ref)
+        assert err < 50 * tol, "request %d: %.2e against the direct sum" % (rid, err)
     srv.close()
