@@ -115,17 +115,30 @@ def breakdown(recs, steps):
     return {k: round(v, 4) for k, v in out.items()}
 
 
-def hbm_roofline(recs):
-    """Stage launches measured against HBM bandwidth (few right-hand sides)."""
+def hbm_roofline(recs, steps=None, ms_per_step=None, side_by_side=False):
+    """Stage launches measured against HBM bandwidth (few right-hand sides).
+
+    With the parts of a multiscale apply side by side, launches overlap and
+    each one's event duration includes the time it shares the chip; then
+    `achieved` is the whole apply's algorithmic bytes (every launch) over the
+    timed wall time per apply, and the per-launch view is kept beside it."""
     stage = [r for r in recs if r["kind"] == 1]
     st_ms = sum(r["ms"] for r in stage)
     st_bytes = sum(r["bytes"] for r in stage)
-    achieved = st_bytes / (st_ms * 1e-3) / 1e9 if st_ms > 0 else 0.0
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "stage block product (16 x 16 tile, few RHS)",
-            "launches": len(stage), "avg_launch_ms": round(st_ms / max(len(stage), 1), 4),
-            "alg_bytes_per_launch_avg": st_bytes / max(len(stage), 1),
-            "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
+    per_launch = st_bytes / (st_ms * 1e-3) / 1e9 if st_ms > 0 else 0.0
+    out = {"bound": "hbm", "achieved": round(per_launch, 1), "peak": 8000.0, "unit": "GB/s",
+           "frac": round(per_launch / 8000.0, 4), "traffic": None,
+           "kernel": "stage block product (16 x 16 tile, few RHS)",
+           "launches": len(stage), "avg_launch_ms": round(st_ms / max(len(stage), 1), 4),
+           "alg_bytes_per_launch_avg": st_bytes / max(len(stage), 1),
+           "kernel_share_of_step": round(st_ms / (sum(r["ms"] for r in recs) or 1.0), 4)}
+    if side_by_side and steps and ms_per_step:
+        all_bytes = sum(r["bytes"] for r in recs) / steps
+        achieved = all_bytes / (ms_per_step * 1e-3) / 1e9
+        out.update({"achieved": round(achieved, 1), "frac": round(achieved / 8000.0, 4),
+                    "kernel": "whole apply, corona parts and center on side streams (stage kernels: 16 x 16 tile)",
+                    "alg_bytes_per_step": all_bytes, "stage_launch_view_gbps": round(per_launch, 1)})
+    return out
 
 
 def measured_traffic(workload, prec):
@@ -280,7 +293,9 @@ def main():
                      "factor_gb_on_device": round(inf.device_bytes / 1e9, 3),
                      "setup_s": round(setup_s, 1),
                      "setup": "load" if args.load else "mbf_build (%s FP64)" % args.builder}
-    out["roofline"] = roofline(recs, args.steps, "c64") if nrhs > 32 else hbm_roofline(recs)
+    side = inf.nparts > 1 and os.environ.get("MBF_PART_STREAMS", "1") != "0"
+    out["roofline"] = roofline(recs, args.steps, "c64") if nrhs > 32 else hbm_roofline(recs, args.steps,
+                                                                                       ms_per_step, side)
     traffic, src = measured_traffic(out["config"]["workload"], "c64")
     out["roofline"]["traffic"] = traffic
     out["roofline"]["traffic_source"] = src
@@ -328,7 +343,8 @@ def main():
         a_total, a_recs = timed_apply(F, h, v, ws, "c64", args.steps, args.warmup, adjoint=True)
         out["adjoint"] = {"value": round(nrhs * args.steps / a_total, 2), "unit": "RHS/s",
                           "ms_per_step": round(1e3 * a_total / args.steps, 4),
-                          "roofline": roofline(a_recs, args.steps, "c64") if nrhs > 32 else hbm_roofline(a_recs),
+                          "roofline": roofline(a_recs, args.steps, "c64") if nrhs > 32 else hbm_roofline(
+                              a_recs, args.steps, 1e3 * a_total / args.steps, side),
                           "ms_per_step_by_kind": breakdown(a_recs, args.steps)}
         log("FP32 adjoint: %.1f RHS/s" % out["adjoint"]["value"])
         del h, v

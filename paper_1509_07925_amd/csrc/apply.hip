@@ -12,8 +12,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "device.h"
 #include "stage_mfma.h"
@@ -695,13 +697,19 @@ int split_state_mode() {
   return e[0] == '0' ? 0 : 1;
 }
 
+// One part of the apply on stream st.  ws holds its two state buffers of
+// buf_ld x nrhs entries each; ws_ld (the widest state of the factorization)
+// keys the split-BF16 state choice.  Forward: the leaf reconstruction, which
+// writes or adds into `out`, waits for `before_out` and records `after_out`
+// (either may be null), so that the parts of a multiscale sum add into u in
+// a fixed order while the rest of their work overlaps.
 template <typename T>
 Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int64_t nrhs, const void* in,
-               int64_t ldin, void* out, int64_t ldout, void* ws, int64_t ws_ld, bool accumulate,
-               hipStream_t st) {
+               int64_t ldin, void* out, int64_t ldout, void* ws, int64_t ws_ld, int64_t buf_ld, bool accumulate,
+               hipStream_t st, hipEvent_t before_out = nullptr, hipEvent_t after_out = nullptr) {
   using C = typename cx<T>::t;
   const PrecData& pd = P.prec[prec];
-  C* buf[2] = {reinterpret_cast<C*>(ws), reinterpret_cast<C*>(ws) + ws_ld * nrhs};
+  C* buf[2] = {reinterpret_cast<C*>(ws), reinterpret_cast<C*>(ws) + buf_ld * nrhs};
   const T* S = reinterpret_cast<const T*>(pd.S);
   const int L = P.L, m = P.m;
   const unsigned nt = ntiles(nrhs);
@@ -724,7 +732,7 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
       // segments of kWideSeg points when their partial sums fit the buffer,
       // else one segment per leaf, summed in place
       int seg = kWideSeg, maxseg = (max_np + kWideSeg - 1) / kWideSeg;
-      const bool two = maxseg > 1 && (int64_t)nleaf * maxseg * max_r <= ws_ld;
+      const bool two = maxseg > 1 && (int64_t)nleaf * maxseg * max_r <= buf_ld;
       if (!two) seg = max_np, maxseg = 1;
       hipLaunchKernelGGL(k_leaf_project_wide<T>,
                          dim3((unsigned)(nleaf * maxseg),
@@ -792,10 +800,12 @@ Error run_part(const DevPart& P, int pidx, Profiler* pr, int prec, bool adj, int
                            P.ld[s], buf[(s + 1) & 1], P.ld[s + 1], ni, sc);
       }
     }
+    if (before_out && hipStreamWaitEvent(st, before_out, 0) != hipSuccess) return {MBF_ERR_HIP, "hipStreamWaitEvent"};
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 2, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
       reconstruct(u_small, P.n_uleaf, P.max_unp, P.d_uleaf, Uf, P.d_uidx, buf[L & 1], P.ld[L], accumulate ? 1 : 0);
     }
+    if (after_out && hipEventRecord(after_out, st) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
   } else {
     if (P.n_uleaf > 0) {
       Timed t(pr, st, 0, pidx, L, prec, 8.0 * P.u_elems * nr, P.u_elems * es + (P.nx + P.rows[L]) * nr * es);
@@ -944,15 +954,46 @@ Error autotune_factor(const DevFactor& F, int prec, int64_t nrhs, void* ws, size
   return {MBF_OK, ""};
 }
 
-size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs) {
+namespace {
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+int64_t part_ld_max(const DevPart& P) {
+  int64_t mx = 4;
+  for (auto v : P.ld) mx = std::max(mx, v);
+  return mx;
+}
+
+size_t center_partial_bytes(const DevFactor& F, int64_t nrhs, size_t es) {
+  if (F.n_center <= 0) return 0;
+  const int64_t ch = center_chunk_rows(F.nx);
+  const size_t nchunk = (size_t)((F.nx + ch - 1) / ch);
+  return nchunk * (size_t)F.n_center * (size_t)nrhs * es;
+}
+
+// Workspace of the parts one after the other: two state buffers of the
+// widest state, which the center's partial sums reuse.
+size_t workspace_bytes_seq(const DevFactor& F, int prec, int64_t nrhs) {
   const size_t es = prec == MBF_C128 ? 16 : 8;
-  size_t b = 2 * (size_t)state_ld_max(F) * (size_t)nrhs * es;
-  if (F.n_center > 0) {
-    const int64_t ch = center_chunk_rows(F.nx);
-    const size_t nchunk = (size_t)((F.nx + ch - 1) / ch);
-    b = std::max(b, nchunk * (size_t)F.n_center * (size_t)nrhs * es);
+  return align256(std::max(2 * (size_t)state_ld_max(F) * (size_t)nrhs * es, center_partial_bytes(F, nrhs, es)));
+}
+
+// Workspace of the parts side by side: two state buffers per part, then the
+// center's partial sums.  Offsets of the regions in `off` (parts, center).
+size_t workspace_bytes_par(const DevFactor& F, int prec, int64_t nrhs, std::vector<size_t>* off) {
+  const size_t es = prec == MBF_C128 ? 16 : 8;
+  size_t b = 0;
+  for (const auto& P : F.parts) {
+    if (off) off->push_back(b);
+    b += align256(2 * (size_t)part_ld_max(P) * (size_t)nrhs * es);
   }
-  return (b + 255) / 256 * 256;
+  if (off) off->push_back(b);
+  return b + align256(center_partial_bytes(F, nrhs, es));
+}
+}  // namespace
+
+size_t workspace_bytes(const DevFactor& F, int prec, int64_t nrhs) {
+  const size_t seq = workspace_bytes_seq(F, prec, nrhs);
+  return F.parts.size() > 1 ? std::max(seq, workspace_bytes_par(F, prec, nrhs, nullptr)) : seq;
 }
 
 // ------------------------------------------------------------------ scratch
@@ -994,7 +1035,7 @@ size_t scratch_bytes() { return kScratchBytes; }
 
 Error launch_apply_scratch(const DevFactor& F, int prec, int64_t nrhs, const void* in, int64_t ldin, void* out,
                            int64_t ldout, hipStream_t st) {
-  const size_t need = workspace_bytes(F, prec, nrhs);
+  const size_t need = workspace_bytes_seq(F, prec, nrhs);  // the parts run one after the other here
   if (need > kScratchBytes)
     return {MBF_ERR_INVALID_ARG, "apply needs " + std::to_string(need) + " bytes of workspace, above the " +
                                      std::to_string(kScratchBytes) + "-byte device scratch: use mbf_apply"};
@@ -1004,10 +1045,111 @@ Error launch_apply_scratch(const DevFactor& F, int prec, int64_t nrhs, const voi
   return launch_apply(F, prec, false, nrhs, in, ldin, out, ldout, ws, kScratchBytes, st);
 }
 
+namespace {
+// Side streams of one caller stream (per device) for the parts of a
+// multiscale apply: the coronas' butterflies and the dense center of
+// eq. (f1) are independent until their sums meet in u, so they run side by
+// side.  Created on first use (default priority, non-blocking) and kept for
+// the life of the process; `fork` orders them after the caller's earlier
+// work, `done[i]` marks the end of side stream i's share.
+struct SideStreams {
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
+};
+std::mutex g_side_mu;
+std::map<std::pair<int, hipStream_t>, SideStreams> g_side;
+
+Error side_streams(hipStream_t caller, size_t n, SideStreams** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return {MBF_ERR_HIP, "hipGetDevice"};
+  std::lock_guard<std::mutex> g(g_side_mu);
+  SideStreams& S = g_side[{dev, caller}];
+  if (!S.fork && hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) != hipSuccess) {
+    S.fork = nullptr;
+    return {MBF_ERR_HIP, "hipEventCreateWithFlags"};
+  }
+  while (S.st.size() < n) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return {MBF_ERR_HIP, "hipStreamCreate"};
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      return {MBF_ERR_HIP, "hipEventCreateWithFlags"};
+    }
+    S.st.push_back(s);
+    S.done.push_back(e);
+  }
+  *out = &S;
+  return {MBF_OK, ""};
+}
+
+// MBF_PART_STREAMS=0 runs the parts of a multiscale apply one after the other.
+bool parts_side_by_side() {
+  const char* e = std::getenv("MBF_PART_STREAMS");
+  return !(e && e[0] == '0');
+}
+
+// The multiscale apply with its parts side by side (see SideStreams).
+// Forward: the center writes u first, then every part adds its sum in part
+// order (each reconstruction waits for the previous one), the same order as
+// one after the other, so the results are identical.  Adjoint: the parts
+// and the center write disjoint entries of v and need no order.
+template <typename T>
+Error apply_side_by_side(const DevFactor& F, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
+                         void* out, int64_t ldout, void* ws, hipStream_t st) {
+  const size_t np = F.parts.size();
+  const bool center = F.n_center > 0;
+  SideStreams* S = nullptr;
+  Error e = side_streams(st, np + (center ? 1 : 0), &S);
+  if (e.st != MBF_OK) return e;
+  std::vector<size_t> off;
+  (void)workspace_bytes_par(F, prec, nrhs, &off);
+  char* base = reinterpret_cast<char*>(ws);
+  if (hipEventRecord(S->fork, st) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
+  for (size_t i = 0; i < np + (center ? 1 : 0); ++i)
+    if (hipStreamWaitEvent(S->st[i], S->fork, 0) != hipSuccess) return {MBF_ERR_HIP, "hipStreamWaitEvent"};
+  const int64_t ws_ld = state_ld_max(F);
+  hipEvent_t prev = nullptr;  // forward: the last writer of u so far
+  if (center) {
+    hipStream_t cs = S->st[np];
+    e = run_center<T>(F, prec, adj, nrhs, in, ldin, out, ldout, base + off[np], false, cs);
+    if (e.st != MBF_OK) return e;
+    if (hipEventRecord(S->done[np], cs) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
+    prev = S->done[np];
+  }
+  for (size_t i = 0; i < np; ++i) {
+    const auto& P = F.parts[i];
+    const bool acc = !adj && (center || i > 0);
+    e = run_part<T>(P, (int)i, &F.prof, prec, adj, nrhs, in, ldin, out, ldout, base + off[i], ws_ld,
+                    part_ld_max(P), acc, S->st[i], adj ? nullptr : prev, adj ? nullptr : S->done[i]);
+    if (e.st != MBF_OK) return e;
+    if (adj && hipEventRecord(S->done[i], S->st[i]) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
+    prev = S->done[i];
+  }
+  // join: forward, the last reconstruction closes the chain; adjoint, every side stream
+  if (!adj) return hipStreamWaitEvent(st, prev, 0) == hipSuccess ? Error{MBF_OK, ""} : Error{MBF_ERR_HIP, "join"};
+  for (size_t i = 0; i < np + (center ? 1 : 0); ++i)
+    if (hipStreamWaitEvent(st, S->done[i], 0) != hipSuccess) return {MBF_ERR_HIP, "hipStreamWaitEvent"};
+  return {MBF_OK, ""};
+}
+}  // namespace
+
 Error launch_apply(const DevFactor& F, int prec, bool adj, int64_t nrhs, const void* in, int64_t ldin,
                    void* out, int64_t ldout, void* ws, size_t ws_bytes, hipStream_t st) {
   if (nrhs <= 0) return {MBF_OK, ""};
-  if (ws_bytes < workspace_bytes(F, prec, nrhs)) return {MBF_ERR_INVALID_ARG, "workspace too small"};
+  if (ws_bytes < workspace_bytes_seq(F, prec, nrhs)) return {MBF_ERR_INVALID_ARG, "workspace too small"};
+  if (F.parts.size() > 1 && parts_side_by_side() && ws_bytes >= workspace_bytes_par(F, prec, nrhs, nullptr)) {
+    // not while the caller's stream is being captured into a graph: the
+    // side streams would have to join the capture
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      Error e = prec == MBF_C128 ? apply_side_by_side<double>(F, prec, adj, nrhs, in, ldin, out, ldout, ws, st)
+                                 : apply_side_by_side<float>(F, prec, adj, nrhs, in, ldin, out, ldout, ws, st);
+      if (e.st != MBF_OK) return e;
+      return hip_check("apply launch");
+    }
+  }
   const int64_t ws_ld = state_ld_max(F);
   bool acc = false;
   if (F.n_center > 0 && !adj) {
@@ -1019,9 +1161,9 @@ Error launch_apply(const DevFactor& F, int prec, bool adj, int64_t nrhs, const v
   for (size_t i = 0; i < F.parts.size(); ++i) {
     const auto& P = F.parts[i];
     Error e = prec == MBF_C128 ? run_part<double>(P, (int)i, &F.prof, prec, adj, nrhs, in, ldin, out, ldout, ws,
-                                                  ws_ld, acc && !adj, st)
+                                                  ws_ld, ws_ld, acc && !adj, st)
                                : run_part<float>(P, (int)i, &F.prof, prec, adj, nrhs, in, ldin, out, ldout, ws,
-                                                 ws_ld, acc && !adj, st);
+                                                 ws_ld, ws_ld, acc && !adj, st);
     if (e.st != MBF_OK) return e;
     acc = true;
   }
