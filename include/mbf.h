@@ -266,7 +266,17 @@ mbf_status mbf_workspace_size(mbf_factor f, mbf_prec p, int64_t nrhs, size_t* by
  * the precision's vector type (complex128 for MBF_C128, complex64
  * otherwise).  Overwrites u.  Errors: MBF_ERR_INVALID_ARG (null pointer,
  * ld too small, workspace too small), MBF_ERR_UNSUPPORTED (precision not in
- * the factor's mask), MBF_ERR_HIP (launch failure). */
+ * the factor's mask), MBF_ERR_HIP (launch failure).
+ * Multiscale factorizations (eq. (f1)): with a workspace of
+ * mbf_workspace_size bytes, the coronas' parts and the dense center run on
+ * side streams of `stream` (created on the first call with that stream and
+ * device, kept until the process ends), ordered after the work already on
+ * `stream` and joined back into it before the call returns; the sums are
+ * added into u in the same order as one after the other, so results do not
+ * depend on it.  While `stream` is being captured into a graph, or with
+ * MBF_PART_STREAMS=0, or with a workspace that only holds the parts one after
+ * the other, everything runs on `stream`.  Calls on one stream must come
+ * from one host thread at a time. */
 mbf_status mbf_apply(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int64_t ldg, void* u,
                      int64_t ldu, void* workspace, size_t ws_bytes, void* stream);
 
@@ -287,7 +297,9 @@ mbf_status mbf_apply_scratch(mbf_factor f, mbf_prec p, int64_t nrhs, const void*
 size_t mbf_scratch_bytes(void);
 
 /* v = K^* h: the chain of eq. (gbf) in reverse order with every factor
- * conjugate-transposed.  h: nx x nrhs (ld ldh), v: nxi x nrhs (ld ldv). */
+ * conjugate-transposed.  h: nx x nrhs (ld ldh), v: nxi x nrhs (ld ldv).
+ * Streams, workspace and errors as mbf_apply (the multiscale parts write
+ * disjoint entries of v). */
 mbf_status mbf_apply_adjoint(mbf_factor f, mbf_prec p, int64_t nrhs, const void* h, int64_t ldh,
                              void* v, int64_t ldv, void* workspace, size_t ws_bytes, void* stream);
 
