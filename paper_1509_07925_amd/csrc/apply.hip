@@ -1084,6 +1084,24 @@ Error side_streams(hipStream_t caller, size_t n, SideStreams** out) {
   return {MBF_OK, ""};
 }
 
+}  // namespace
+
+void release_side_streams(hipStream_t caller) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> g(g_side_mu);
+  auto it = g_side.find({dev, caller});
+  if (it == g_side.end()) return;
+  for (size_t i = 0; i < it->second.st.size(); ++i) {
+    (void)hipStreamSynchronize(it->second.st[i]);
+    (void)hipStreamDestroy(it->second.st[i]);
+    (void)hipEventDestroy(it->second.done[i]);
+  }
+  if (it->second.fork) (void)hipEventDestroy(it->second.fork);
+  g_side.erase(it);
+}
+
+namespace {
 // MBF_PART_STREAMS=0 runs the parts of a multiscale apply one after the other.
 bool parts_side_by_side() {
   const char* e = std::getenv("MBF_PART_STREAMS");

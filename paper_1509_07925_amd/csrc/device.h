@@ -125,6 +125,10 @@ Error launch_apply(const DevFactor& F, int prec, bool adjoint, int64_t nrhs, con
 Error launch_apply_scratch(const DevFactor& F, int prec, int64_t nrhs, const void* in, int64_t ldin, void* out,
                            int64_t ldout, hipStream_t stream);
 size_t scratch_bytes();
+// Destroy the side streams that multiscale applies created for the caller
+// stream `caller` on the current device (after they drain); a caller that
+// destroys its stream calls this first.
+void release_side_streams(hipStream_t caller);
 
 }  // namespace mbf
 

@@ -552,13 +552,18 @@ void mbf_server_destroy(mbf_server srv) {
   }
   s->cv.notify_all();
   if (s->th.joinable()) s->th.join();
+  int prev = 0;
+  const bool switch_dev = hipGetDevice(&prev) == hipSuccess && prev != s->device;
+  if (switch_dev) (void)hipSetDevice(s->device);  // the side streams were made on the server's device
   for (auto& sl : s->slots) {
     (void)hipStreamSynchronize(sl.stream);
     sl.drop_graphs();
+    mbf::release_side_streams(sl.stream);
     (void)hipStreamDestroy(sl.stream);
     (void)hipEventDestroy(sl.done);
   }
   (void)hipFree(s->pool.base);
+  if (switch_dev) (void)hipSetDevice(prev);
   delete s;
 }
 
