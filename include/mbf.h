@@ -85,7 +85,11 @@ typedef int (*mbf_entry_cb)(void* user, int64_t m, const int64_t* rows, int64_t 
  *                    K = exp(2 pi i Phi), Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),
  *                    c1 = c_scale (2 + sin 2pi x1 sin 2pi x2)/16,
  *                    c2 = c_scale (2 + cos 2pi x1 cos 2pi x2)/16,
- *                    x = (n1/n, n2/n), xi integer.                       */
+ *                    x = (n1/n, n2/n), xi integer.
+ *   mbf_kernel_fio_points: the same kernel for arbitrary real points x and
+ *                    xi (general point sets): Phi evaluated directly in
+ *                    FP64, without the grids' exact reduction of x.xi
+ *                    (n unused).                                         */
 typedef struct {
   int64_t n;        /* grid side */
   double c_scale;   /* FIO only: 1 = Example 1, 0 = linear phase x.xi */
@@ -96,6 +100,8 @@ int mbf_kernel_dft(void* user, int64_t m, const int64_t* rows, int64_t k, const 
                    double* out);
 int mbf_kernel_fio(void* user, int64_t m, const int64_t* rows, int64_t k, const int64_t* cols,
                    double* out);
+int mbf_kernel_fio_points(void* user, int64_t m, const int64_t* rows, int64_t k, const int64_t* cols,
+                          double* out);
 
 /* Build options.
  *   tol        block-relative truncation: keep sigma_k > tol * sigma_1
@@ -104,7 +110,12 @@ int mbf_kernel_fio(void* user, int64_t m, const int64_t* rows, int64_t k, const 
  *   depth      tree depth L (both trees).  0 = automatic: uniform leaves of
  *              leaf_side x leaf_side points on a grid of side n.
  *   leaf_side  leaf side for depth = 0 (power of two dividing n).
- *   grid_n     side n of the grids (needed by the polar and multiscale maps).
+ *   grid_n     side n of the grids (needed by the polar and multiscale maps);
+ *              0 = general point sets (Section 2.6): the trees cover the
+ *              bounding squares of X and Omega (Omega through the polar map
+ *              with R = max |xi| for MBF_SPLIT_POLAR) to the given depth
+ *              (>= 1), nodes without points are dropped; host builder only,
+ *              no multiscale split.
  *   split      MBF_SPLIT_*.
  *   center_side multiscale only: side of the dense center square Omega_C
  *              (Section 4.3 uses 16).
@@ -287,8 +298,10 @@ mbf_status mbf_apply(mbf_factor f, mbf_prec p, int64_t nrhs, const void* g, int6
  * 128 MiB; one copy per device, held until the process ends) instead of the
  * caller's workspace.  Arguments as for mbf_apply.  Errors as mbf_apply,
  * plus MBF_ERR_INVALID_ARG when the apply needs more workspace than the
- * scratch holds (mbf_workspace_size(f, p, nrhs) > mbf_scratch_bytes(); use
- * mbf_apply then).  The first call on a device looks up the scratch's
+ * scratch holds (use mbf_apply then).  A multiscale factorization's parts
+ * run one after the other on `stream` here (no side streams), which needs
+ * at most mbf_workspace_size(f, p, nrhs) bytes, less when the parts would
+ * otherwise run side by side.  The first call on a device looks up the scratch's
  * address there.  All calls on one device share its scratch: calls that
  * overlap on one device (concurrent streams or threads) race and must be
  * serialized by the caller. */

@@ -57,3 +57,24 @@ def poisson_arrivals(nreq, rate_per_s, seed=0):
     """Arrival times (seconds) of a Poisson stream with the given rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate_per_s, size=nreq))
+
+
+def clustered_points(npts, seed=0, k=5, width=0.08):
+    """Non-uniform points of [0,1)^2 (general point sets, Section 2.6): a
+    mixture of k Gaussian clusters of the given width around uniformly drawn
+    centres, folded into the unit square; shape (npts, 2)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.random((k, 2))
+    which = rng.integers(0, k, size=npts)
+    p = centres[which] + width * rng.standard_normal((npts, 2))
+    return np.mod(p, 1.0)
+
+
+def disk_frequencies(npts, radius, seed=0):
+    """Non-uniform frequencies in the disk |xi| < radius, denser towards the
+    origin (radius drawn as radius * u^2 for uniform u, angle uniform);
+    shape (npts, 2)."""
+    rng = np.random.default_rng(seed)
+    r = radius * rng.random(npts) ** 2
+    t = 2.0 * np.pi * rng.random(npts)
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)

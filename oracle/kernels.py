@@ -68,6 +68,19 @@ def fio_radon(n, c_scale=1.0):
     return K
 
 
+def fio_points(c_scale=1.0):
+    """Example 1 FIO kernel exp(2 pi i Phi(x, xi)) of eq. (example1phi) for
+    arbitrary real points x and xi (general point sets): the phase is
+    evaluated directly, without the grid's exact reduction of x . xi."""
+    Phi = fio_phase(c_scale)
+
+    def K(x, xi):
+        ph = Phi(x, xi)
+        return np.exp(2j * np.pi * (ph - np.floor(ph)))
+
+    return K
+
+
 def restrict(K, x, xi):
     """Entry function over index sets: f(I, J) = K(x[I], xi[J])."""
 

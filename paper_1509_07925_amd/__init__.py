@@ -79,7 +79,7 @@ MATVEC_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctyp
 
 EXPORTS = ["mbf_build", "mbf_import", "mbf_multiscale_assemble", "mbf_workspace_size", "mbf_apply",
            "mbf_apply_adjoint", "mbf_info", "mbf_destroy", "mbf_last_error", "mbf_kernel_dft",
-           "mbf_kernel_fio", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
+           "mbf_kernel_fio", "mbf_kernel_fio_points", "mbf_profile_begin", "mbf_profile_end", "mbf_server_create",
            "mbf_server_submit", "mbf_server_poll", "mbf_server_drain", "mbf_server_stats",
            "mbf_server_destroy", "mbf_save", "mbf_load", "mbf_autotune", "mbf_apply_scratch", "mbf_scratch_bytes",
            "mbf_build_matvec"]
@@ -184,19 +184,23 @@ class Factor:
               device_mem_gb=0):
         """mbf_build from point sets and a kernel-entry callback.
 
-        ``kernel`` is "dft", "fio" (built-in C callbacks) or a Python
+        ``n`` is the side of the grids; 0 builds on general point sets (the
+        trees cover the points' bounding squares to ``depth`` levels).
+
+        ``kernel`` is "dft", "fio", "fio_points" (built-in C callbacks; the
+        last one for general point sets) or a Python
         callable f(rows, cols) -> complex128 array (rows x cols) taking
         index arrays into x / xi.  ``builder`` is "device" (FP64 on the GPU;
         built-in kernels only, tol >= 1e-7) or "host"; by default built-in
         kernels build on the device and Python callables on the host.
         """
         if builder is None:
-            builder = "device" if kernel in ("dft", "fio") else "host"
+            builder = "device" if kernel in ("dft", "fio") and n > 0 else "host"
         x = np.ascontiguousarray(x, np.float64)
         xi = np.ascontiguousarray(xi, np.float64)
         L = lib()
         keep = [x, xi]
-        if kernel in ("dft", "fio"):
+        if kernel in ("dft", "fio", "fio_points"):
             params = _KParams(n, c_scale, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
             fn = getattr(L, "mbf_kernel_" + kernel)

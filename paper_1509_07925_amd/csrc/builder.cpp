@@ -20,6 +20,7 @@
 #include <exception>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <random>
 #include <thread>
 #include <sched.h>
@@ -394,7 +395,12 @@ bool validate_opts(const mbf_opts& o, std::string& why) {
   if (o.depth < 0 || o.depth > 14) return why = "depth must be in [0, 14]", false;
   if (o.depth == 0 && (o.leaf_side < 1 || (o.leaf_side & (o.leaf_side - 1))))
     return why = "leaf_side must be a power of two", false;
-  if (o.grid_n < 2 || (o.grid_n & (o.grid_n - 1))) return why = "grid_n must be a power of two >= 2", false;
+  if (o.grid_n == 0) {  // general point sets
+    if (o.depth < 1) return why = "general point sets (grid_n = 0) need depth >= 1", false;
+    if (o.split == MBF_SPLIT_MULTISCALE) return why = "the multiscale split needs grid points (grid_n > 0)", false;
+  } else if (o.grid_n < 2 || (o.grid_n & (o.grid_n - 1))) {
+    return why = "grid_n must be a power of two >= 2, or 0 for general point sets", false;
+  }
   if (o.split < MBF_SPLIT_NONE || o.split > MBF_SPLIT_MULTISCALE) return why = "unknown split", false;
   if (o.split == MBF_SPLIT_MULTISCALE && (o.center_side < 2 || (o.center_side & (o.center_side - 1))))
     return why = "center_side must be a power of two >= 2", false;
@@ -687,9 +693,86 @@ Error finish_device_part(const Tree& xt, const Tree& ot, const std::vector<int64
 
 }  // namespace
 
+namespace {
+// Leaf codes of points in a square: cell (floor((p - lo) / side * 2^L)),
+// the last cell closed, Morton-ordered (Fig. 1).
+std::vector<int64_t> square_leaf_codes(int64_t np, const double* p, double lo0, double lo1, double side, int L) {
+  const int64_t nl = (int64_t)1 << L;
+  const double sc = (double)nl / side;
+  std::vector<int64_t> c(np);
+  for (int64_t i = 0; i < np; ++i) {
+    const int64_t c1 = std::min<int64_t>(std::max<int64_t>((int64_t)std::floor((p[2 * i] - lo0) * sc), 0), nl - 1);
+    const int64_t c2 = std::min<int64_t>(std::max<int64_t>((int64_t)std::floor((p[2 * i + 1] - lo1) * sc), 0), nl - 1);
+    c[i] = morton2(c1, c2, L);
+  }
+  return c;
+}
+
+// Smallest axis-aligned square holding every point (false on a non-finite coordinate).
+bool bounding_square(int64_t np, const double* p, double& lo0, double& lo1, double& side) {
+  double a0 = INFINITY, a1 = INFINITY, b0 = -INFINITY, b1 = -INFINITY;
+  for (int64_t i = 0; i < np; ++i) {
+    const double u = p[2 * i], v = p[2 * i + 1];
+    if (!std::isfinite(u) || !std::isfinite(v)) return false;
+    a0 = std::min(a0, u), b0 = std::max(b0, u), a1 = std::min(a1, v), b1 = std::max(b1, v);
+  }
+  lo0 = a0, lo1 = a1;
+  side = std::max(b0 - a0, b1 - a1);
+  if (!(side > 0)) side = 1.0;
+  return true;
+}
+
+// General point sets (Section 2.6: the trees follow the points and drop
+// empty nodes): X and Omega in their bounding squares, or Omega through the
+// polar map p = (|xi| / R, angle / 2 pi mod 1) with R = max |xi| (Section
+// 3.2), both of depth opts.depth; one part, built on the host.
+Error build_general(int64_t nx, const double* x, int64_t nxi, const double* xi, mbf_entry_cb cb, void* user,
+                    const mbf_opts& o, DevFactor& F, const MatvecSource* src) {
+  if (o.builder != MBF_BUILD_HOST) return {MBF_ERR_UNSUPPORTED, "general point sets build on the host"};
+  const int L = o.depth;
+  double lo0, lo1, side;
+  if (!bounding_square(nx, x, lo0, lo1, side)) return {MBF_ERR_INVALID_ARG, "non-finite X coordinate"};
+  std::vector<int64_t> xc = square_leaf_codes(nx, x, lo0, lo1, side, L);
+  std::vector<int64_t> oc;
+  if (o.split == MBF_SPLIT_POLAR) {
+    double R = 0.0;
+    for (int64_t i = 0; i < nxi; ++i) {
+      const double r = std::hypot(xi[2 * i], xi[2 * i + 1]);
+      if (!std::isfinite(r)) return {MBF_ERR_INVALID_ARG, "non-finite Omega coordinate"};
+      R = std::max(R, r);
+    }
+    if (!(R > 0)) R = 1.0;
+    std::vector<double> pp((size_t)(2 * nxi));
+    for (int64_t i = 0; i < nxi; ++i) {
+      const double a = xi[2 * i], b = xi[2 * i + 1];
+      double p2 = (a == 0.0 && b == 0.0) ? 0.0 : std::atan2(b, a) / (2.0 * M_PI);
+      pp[2 * i] = std::hypot(a, b) / R;
+      pp[2 * i + 1] = p2 - std::floor(p2);
+    }
+    oc = square_leaf_codes(nxi, pp.data(), 0.0, 0.0, 1.0, L);
+  } else {
+    if (!bounding_square(nxi, xi, lo0, lo1, side)) return {MBF_ERR_INVALID_ARG, "non-finite Omega coordinate"};
+    oc = square_leaf_codes(nxi, xi, lo0, lo1, side, L);
+  }
+  std::vector<int64_t> xs(nx), os(nxi);
+  std::iota(xs.begin(), xs.end(), 0);
+  std::iota(os.begin(), os.end(), 0);
+  Tree xt = tree_from_leaf_codes(L, nx, xc.data());
+  Tree ot = tree_from_leaf_codes(L, nxi, oc.data());
+  HostFactor f = build_host_impl(xt, ot, xs, os, cb, user, o, src);
+  return finish_part(f, nullptr, F.prec_mask, F);
+}
+}  // namespace
+
 Error build_factor(int64_t nx, const double* x, int64_t nxi, const double* xi, mbf_entry_cb cb, void* user,
                    const mbf_opts& o, DevFactor& F, const MatvecSource* src) {
   const int64_t n = o.grid_n;
+  if (n == 0) {
+    F.nx = nx;
+    F.nxi = nxi;
+    F.prec_mask = o.prec_mask & 7u;
+    return build_general(nx, x, nxi, xi, cb, user, o, F, src);
+  }
   if (nx != n * n || nxi != n * n) return {MBF_ERR_INVALID_ARG, "points must form n x n grids (grid_n)"};
   if (src && o.builder != MBF_BUILD_HOST) return {MBF_ERR_UNSUPPORTED, "the matvec build runs on the host builder"};
   // Device builder: the entries are evaluated on the GPU, so the kernel must
@@ -835,6 +918,30 @@ extern "C" int mbf_kernel_dft(void* user, int64_t m, const int64_t* rows, int64_
       const double ph = -2.0 * M_PI * ((double)q / (double)n);
       out[2 * (a + b * m)] = std::cos(ph);
       out[2 * (a + b * m) + 1] = std::sin(ph);
+    }
+  }
+  return 0;
+}
+
+extern "C" int mbf_kernel_fio_points(void* user, int64_t m, const int64_t* rows, int64_t k, const int64_t* cols,
+                                     double* out) {
+  const auto* p = static_cast<const mbf_kernel_params*>(user);
+  if (!p || !p->x || !p->xi) return 1;
+  std::vector<double> c1(m), c2(m), y1(m), y2(m);
+  for (int64_t a = 0; a < m; ++a) {
+    const double x1 = p->x[2 * rows[a]], x2 = p->x[2 * rows[a] + 1];
+    c1[a] = p->c_scale * (2.0 + std::sin(2.0 * M_PI * x1) * std::sin(2.0 * M_PI * x2)) / 16.0;
+    c2[a] = p->c_scale * (2.0 + std::cos(2.0 * M_PI * x1) * std::cos(2.0 * M_PI * x2)) / 16.0;
+    y1[a] = x1;
+    y2[a] = x2;
+  }
+  for (int64_t b = 0; b < k; ++b) {
+    const double w1 = p->xi[2 * cols[b]], w2 = p->xi[2 * cols[b] + 1];
+    for (int64_t a = 0; a < m; ++a) {
+      const double ph = y1[a] * w1 + y2[a] * w2 + std::sqrt(c1[a] * c1[a] * w1 * w1 + c2[a] * c2[a] * w2 * w2);
+      const double arg = 2.0 * M_PI * (ph - std::floor(ph));
+      out[2 * (a + b * m)] = std::cos(arg);
+      out[2 * (a + b * m) + 1] = std::sin(arg);
     }
   }
   return 0;

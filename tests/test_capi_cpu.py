@@ -300,3 +300,42 @@ def test_matvec_build_probes_are_zero_padded_gaussians():
             np.testing.assert_array_equal(part[rows], P[rows])
             covered[rows] += 1
         assert np.all(covered == 1)
+
+
+def test_point_set_kernel_matches_oracle_definition():
+    """mbf_kernel_fio_points (general point sets) against the oracle's
+    direct evaluation of eq. (example1phi) on clustered x and non-grid xi,
+    and against the grid kernel on grid points."""
+    x = W.clustered_points(300, seed=3)
+    xi = W.disk_frequencies(200, 32.0, seed=4)
+    rows, cols = np.arange(0, 300, 7), np.arange(0, 200, 3)
+    got = _call_kernel("mbf_kernel_fio_points", 0, x, xi, rows, cols)
+    np.testing.assert_allclose(got, kernels.fio_points()(x[rows], xi[cols]), atol=1e-11)
+    n = 32
+    xu, xg = W.grid_x_unit(n), W.grid_omega(n)
+    rows, cols = W.sample_rows(n * n, 40, seed=1), W.sample_rows(n * n, 30, seed=2)
+    got = _call_kernel("mbf_kernel_fio_points", n, xu, xg, rows, cols)
+    np.testing.assert_allclose(got, kernels.fio_radon(n)(xu[rows], xg[cols]), atol=1e-11)
+
+
+def test_general_point_set_options_and_host_build_without_gpu():
+    """grid_n = 0 (general point sets) needs a depth, refuses the multiscale
+    split and the device builder before any work; with valid options the
+    host build runs its whole factorization (on a machine without a GPU the
+    upload of the factors then fails)."""
+    x = np.ascontiguousarray(W.clustered_points(256, seed=5))
+    xi = np.ascontiguousarray(W.disk_frequencies(256, 8.0, seed=6))
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.build(x, xi, 0, kernel="fio_points", depth=0)
+    assert e.value.status == -1 and "depth" in str(e.value)
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.build(x, xi, 0, kernel="fio_points", depth=3, split="multiscale")
+    assert e.value.status == -1
+    with pytest.raises(mbf.MBFError) as e:
+        mbf.Factor.build(x, xi, 0, kernel="fio_points", depth=3, builder="device")
+    assert e.value.status == -5
+    for split in ("none", "polar"):
+        try:
+            mbf.Factor.build(x, xi, 0, kernel="fio_points", depth=3, split=split, tol=1e-8, builder="host")
+        except mbf.MBFError as e:
+            assert e.status in (-2, -4), e

@@ -189,3 +189,34 @@ def test_planted_mistake_unconjugated_adjoint_is_caught(monkeypatch):
     Kd = kernels.dft(8)(W.grid_x_integer(8), W.grid_omega(8))
     h = W.rhs(64, 1, seed=2)
     assert direct.rel_err(bf.adjoint(h), Kd.conj().T @ h) > 1e-3
+
+
+def _bounding(p):
+    lo = p.min(axis=0)
+    return (lo[0], lo[1]), float((p.max(axis=0) - lo).max())
+
+
+def test_general_point_sets_full_rank_equals_dense():
+    """General point sets (Section 2.6): clustered X and non-grid Omega in a
+    disk, trees over the bounding squares with empty nodes dropped, plain and
+    polar Omega trees; at full rank the factorization reproduces the dense
+    kernel (brute force) forward and adjoint."""
+    x = W.clustered_points(400, seed=7)
+    xi = W.disk_frequencies(300, 12.0, seed=8)
+    K = kernels.fio_points()
+    Kd = K(x, xi)
+    g, h = W.rhs(300, 3, seed=9), W.rhs(400, 3, seed=10)
+    r = np.hypot(xi[:, 0], xi[:, 1])
+    polar = np.stack([r / r.max(), np.mod(np.arctan2(xi[:, 1], xi[:, 0]) / (2 * np.pi), 1.0)], axis=1)
+    for pts, obox in ((xi, _bounding(xi)), (polar, ((0.0, 0.0), 1.0))):
+        ent = lambda I, J: K(x[I], xi[J])
+        bf = butterfly.Butterfly.build(ent, x, pts, _bounding(x), obox, 3, 1e-14, 10 ** 6, method="exact")
+        assert len(bf.xt.nodes[3]) < 64 and len(bf.ot.nodes[3]) <= 64  # empty leaves dropped
+        assert direct.rel_err(bf.apply(g), Kd @ g) < 1e-11
+        assert direct.rel_err(bf.adjoint(h), Kd.conj().T @ h) < 1e-11
+
+
+def test_point_set_kernel_agrees_with_grid_kernel_on_grids():
+    n = 16
+    x, xi = W.grid_x_unit(n), W.grid_omega(n)
+    np.testing.assert_allclose(kernels.fio_points()(x, xi), kernels.fio_radon(n)(x, xi), atol=1e-11)
