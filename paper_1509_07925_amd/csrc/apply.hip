@@ -1118,38 +1118,39 @@ Error apply_side_by_side(const DevFactor& F, int prec, bool adj, int64_t nrhs, c
                          void* out, int64_t ldout, void* ws, hipStream_t st) {
   const size_t np = F.parts.size();
   const bool center = F.n_center > 0;
+  const size_t nside = np + (center ? 1 : 0);
   SideStreams* S = nullptr;
-  Error e = side_streams(st, np + (center ? 1 : 0), &S);
+  Error e = side_streams(st, nside, &S);
   if (e.st != MBF_OK) return e;
   std::vector<size_t> off;
   (void)workspace_bytes_par(F, prec, nrhs, &off);
   char* base = reinterpret_cast<char*>(ws);
   if (hipEventRecord(S->fork, st) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
-  for (size_t i = 0; i < np + (center ? 1 : 0); ++i)
-    if (hipStreamWaitEvent(S->st[i], S->fork, 0) != hipSuccess) return {MBF_ERR_HIP, "hipStreamWaitEvent"};
+  size_t forked = 0;
+  for (; forked < nside; ++forked)
+    if (hipStreamWaitEvent(S->st[forked], S->fork, 0) != hipSuccess) break;
+  if (forked < nside) e = {MBF_ERR_HIP, "hipStreamWaitEvent"};
   const int64_t ws_ld = state_ld_max(F);
   hipEvent_t prev = nullptr;  // forward: the last writer of u so far
-  if (center) {
+  if (e.st == MBF_OK && center) {
     hipStream_t cs = S->st[np];
     e = run_center<T>(F, prec, adj, nrhs, in, ldin, out, ldout, base + off[np], false, cs);
-    if (e.st != MBF_OK) return e;
-    if (hipEventRecord(S->done[np], cs) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
+    if (e.st == MBF_OK && hipEventRecord(S->done[np], cs) != hipSuccess) e = {MBF_ERR_HIP, "hipEventRecord"};
     prev = S->done[np];
   }
-  for (size_t i = 0; i < np; ++i) {
+  for (size_t i = 0; i < np && e.st == MBF_OK; ++i) {
     const auto& P = F.parts[i];
     const bool acc = !adj && (center || i > 0);
     e = run_part<T>(P, (int)i, &F.prof, prec, adj, nrhs, in, ldin, out, ldout, base + off[i], ws_ld,
                     part_ld_max(P), acc, S->st[i], adj ? nullptr : prev, adj ? nullptr : S->done[i]);
-    if (e.st != MBF_OK) return e;
-    if (adj && hipEventRecord(S->done[i], S->st[i]) != hipSuccess) return {MBF_ERR_HIP, "hipEventRecord"};
     prev = S->done[i];
   }
-  // join: forward, the last reconstruction closes the chain; adjoint, every side stream
-  if (!adj) return hipStreamWaitEvent(st, prev, 0) == hipSuccess ? Error{MBF_OK, ""} : Error{MBF_ERR_HIP, "join"};
-  for (size_t i = 0; i < np + (center ? 1 : 0); ++i)
-    if (hipStreamWaitEvent(st, S->done[i], 0) != hipSuccess) return {MBF_ERR_HIP, "hipStreamWaitEvent"};
-  return {MBF_OK, ""};
+  // join every side stream that was forked, also after an error, so that no
+  // work of this call is left running behind the caller's stream
+  for (size_t i = 0; i < forked; ++i)
+    if (hipEventRecord(S->done[i], S->st[i]) != hipSuccess || hipStreamWaitEvent(st, S->done[i], 0) != hipSuccess)
+      if (e.st == MBF_OK) e = {MBF_ERR_HIP, "join of the side streams"};
+  return e;
 }
 }  // namespace
 
