@@ -236,7 +236,7 @@ struct Server {
         // one that size, so that the region (and its graphs) stays put
         const size_t full = batch_bytes(head, batch_width(max_batch_rhs, max_batch_rhs));
         const bool roomy = full > need && full <= pool.size / slots.size();
-        if (!(roomy && grow_region(s, full)) && !grow_region(s, need)) return false;  // admission: wait
+        if (!(roomy && grow_region(s, full, false)) && !grow_region(s, need, true)) return false;  // admission: wait
       }
       off = s.fix_off;
     } else {
@@ -307,9 +307,9 @@ struct Server {
 
   // Graph mode: give slot s a fixed region of at least `need` bytes (its
   // graphs point into the old one and are dropped).  When the pool cannot
-  // hold it, the regions of idle slots are released too; false when even
-  // then it does not fit (the batch waits).
-  bool grow_region(Slot& s, size_t need) {
+  // hold it and `evict` is set, the regions of idle slots are released too;
+  // false when it does not fit (the batch waits).
+  bool grow_region(Slot& s, size_t need, bool evict) {
     auto release = [&](Slot& t) {
       t.drop_graphs();
       if (t.fix_off != SIZE_MAX) pool.release(t.fix_off, t.fix_bytes);
@@ -318,7 +318,7 @@ struct Server {
     };
     release(s);
     size_t off = pool.alloc(need);
-    if (off == SIZE_MAX) {
+    if (off == SIZE_MAX && evict) {
       for (auto& t : slots)
         if (&t != &s && !t.busy) release(t);
       off = pool.alloc(need);
