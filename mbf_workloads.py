@@ -78,3 +78,15 @@ def disk_frequencies(npts, radius, seed=0):
     r = radius * rng.random(npts) ** 2
     t = 2.0 * np.pi * rng.random(npts)
     return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+
+
+def grid_integer_nd(n, d):
+    """Integer grid {0..n-1}^d in user order (row-major, first coordinate the
+    slowest), shape (n**d, d), float64."""
+    axes = np.meshgrid(*([np.arange(n)] * d), indexing="ij")
+    return np.stack([a.ravel() for a in axes], axis=1).astype(np.float64)
+
+
+def grid_omega_nd(n, d):
+    """Frequency grid {-n/2..n/2-1}^d in user order, shape (n**d, d)."""
+    return grid_integer_nd(n, d) - float(n // 2)

@@ -45,6 +45,21 @@ def dft_fft(n, g):
     return u[:, 0] if vec else u
 
 
+def dft_fftn(n, d, g):
+    """Closed form of the d-dimensional DFT case (x in {0..n-1}^d, xi in
+    {-n/2..n/2-1}^d, user order row-major): u = fftn(ifftshift(G))."""
+    g = np.asarray(g, dtype=np.complex128)
+    vec = g.ndim == 1
+    if vec:
+        g = g[:, None]
+    nr = g.shape[1]
+    G = g.T.reshape((nr,) + (n,) * d)
+    axes = tuple(range(1, d + 1))
+    U = np.fft.fftn(np.fft.ifftshift(G, axes=axes), axes=axes)
+    u = U.reshape(nr, n ** d).T
+    return u[:, 0] if vec else u
+
+
 def dft_fft_adjoint(n, h):
     """Closed form of K^* h for the 2D DFT case: N * fftshift(ifft2(H))."""
     h = np.asarray(h, dtype=np.complex128)

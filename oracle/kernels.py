@@ -18,14 +18,18 @@ import numpy as np
 
 
 def dft(n):
-    """K(x, xi) = exp(-2 pi i x.xi / n); x, xi integer coordinates."""
+    """K(x, xi) = exp(-2 pi i x.xi / n); x, xi integer coordinates (any
+    dimension: x.xi sums over every coordinate)."""
 
     def K(x, xi):
         x = np.asarray(x, dtype=np.float64)
         xi = np.asarray(xi, dtype=np.float64)
         xi_i = np.rint(xi).astype(np.int64)
         x_i = np.rint(x).astype(np.int64)
-        k = (np.outer(x_i[:, 0], xi_i[:, 0]) + np.outer(x_i[:, 1], xi_i[:, 1])) % n
+        k = np.zeros((x_i.shape[0], xi_i.shape[0]), dtype=np.int64)
+        for j in range(x_i.shape[1]):
+            k += np.outer(x_i[:, j], xi_i[:, j])
+        k %= n
         return np.exp(-2j * np.pi * (k.astype(np.float64) / n))
 
     return K

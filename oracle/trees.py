@@ -19,6 +19,19 @@
 import numpy as np
 
 
+def morton_nd(cells, level):
+    """Z-order index of d-dimensional cells (rows of ``cells``, shape (m, d))
+    at the given level: bit b of coordinate k goes to bit b d + (d - 1 - k),
+    so the first coordinate is the most significant (d = 2: ``morton``)."""
+    cells = np.asarray(cells, dtype=np.int64)
+    d = cells.shape[1]
+    code = np.zeros(cells.shape[0], dtype=np.int64)
+    for b in range(level):
+        for k in range(d):
+            code |= ((cells[:, k] >> b) & 1) << (b * d + d - 1 - k)
+    return code
+
+
 def morton(c1, c2, level):
     """Z-order index of cell (c1, c2) at the given level, c1 more significant."""
     c1 = np.asarray(c1, dtype=np.int64)
@@ -31,7 +44,9 @@ def morton(c1, c2, level):
 
 
 class QuadTree:
-    """Quadtree of a 2D point set inside the box [lo, lo + side)^2.
+    """Quadtree of a 2D point set inside the box [lo, lo + side)^2 (for points
+    of d coordinates, the same 2^d-ary tree over [lo, lo + side)^d: an octree
+    for d = 3, children numbered like ``morton_nd``).
 
     Attributes
     ----------
@@ -46,18 +61,19 @@ class QuadTree:
         pts = np.asarray(pts, dtype=np.float64)
         self.depth = int(depth)
         self.npts = pts.shape[0]
+        self.dim = pts.shape[1]
         lo = np.asarray(lo, dtype=np.float64)
         nl = 1 << self.depth
         t = (pts - lo[None, :]) / float(side)
         c = np.floor(t * nl).astype(np.int64)
         c = np.clip(c, 0, nl - 1)
-        self.leaf_code = morton(c[:, 0], c[:, 1], self.depth)
+        self.leaf_code = morton(c[:, 0], c[:, 1], self.depth) if self.dim == 2 else morton_nd(c, self.depth)
         self.order = np.lexsort((np.arange(self.npts), self.leaf_code))
         sorted_codes = self.leaf_code[self.order]
         self.nodes = []
         self.span = []
         for lev in range(self.depth + 1):
-            codes = sorted_codes >> (2 * (self.depth - lev))
+            codes = sorted_codes >> (self.dim * (self.depth - lev))
             uniq, first = np.unique(codes, return_index=True)
             ends = np.append(first[1:], self.npts)
             self.nodes.append(uniq)
@@ -70,7 +86,8 @@ class QuadTree:
     def children(self, level, code):
         """Nonempty children (codes at level+1) of node ``code`` in Z-order."""
         sp = self.span[level + 1]
-        return [4 * code + t for t in range(4) if (4 * code + t) in sp]
+        nc = 1 << self.dim
+        return [nc * code + t for t in range(nc) if (nc * code + t) in sp]
 
     def child_rows(self, level, code, child):
         """Row range of ``child`` (level+1) inside the point list of ``code``."""
