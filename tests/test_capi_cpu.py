@@ -339,3 +339,15 @@ def test_general_point_set_options_and_host_build_without_gpu():
             mbf.Factor.build(x, xi, 0, kernel="fio_points", depth=3, split=split, tol=1e-8, builder="host")
         except mbf.MBFError as e:
             assert e.status in (-2, -4), e
+
+
+def test_general_point_sets_refuse_non_finite_coordinates():
+    x = np.ascontiguousarray(W.clustered_points(64, seed=7))
+    xi = np.ascontiguousarray(W.disk_frequencies(64, 4.0, seed=8))
+    for bad_x, bad_xi in ((True, False), (False, True)):
+        xb, xib = x.copy(), xi.copy()
+        (xb if bad_x else xib)[3, 1] = np.nan
+        for split in ("none", "polar"):
+            with pytest.raises(mbf.MBFError) as e:
+                mbf.Factor.build(xb, xib, 0, kernel="fio_points", depth=2, split=split, builder="host")
+            assert e.value.status == -1 and "non-finite" in str(e.value)
